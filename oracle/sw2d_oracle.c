@@ -1,0 +1,202 @@
+/*
+ * FP64 CPU oracle for one time step of the 2-D shallow-water model (2DSW).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the package smoke check and the
+ * benchmark's CPU-baseline leg may build, load or call this file. It shares no
+ * code, header or constant with the HIP path.
+ *
+ * What the paper fixes (Sect. 6.2, "Test Case 1: 2-D Shallow Water Model"): the
+ * model is a time loop that calls a predictor ("dyn") and a first-order Shapiro
+ * filter ("shapiro") and then updates the velocity. It gives no equations, so
+ * the discretisation below is a reading of that description:
+ *
+ *  - Arakawa C grid on a closed basin with a static land mask. Every field is a
+ *    row-major [ny][nx] array; u[j][i] lives on the east face of cell (j,i),
+ *    v[j][i] on its north face. A face is active when both cells it joins are
+ *    water; inactive faces carry exactly zero.
+ *  - dyn, part 1 (momentum predictor, pressure gradient only):
+ *        us = u - (g dt/dx) (eta_E - eta),   vs = v - (g dt/dy) (eta_N - eta)
+ *  - dyn, part 2 (free surface from the flux divergence, forward-backward in
+ *    time: the fluxes use the predicted velocities and the total depth
+ *    h = H + eta of the old surface, upwinded by the sign of the face velocity):
+ *        es = eta - (dt/dx)(Fx_e - Fx_w) - (dt/dy)(Fy_n - Fy_s)
+ *  - shapiro (first-order, five-point, only across active faces):
+ *        eta' = es + (eps/4) * sum over water neighbours (es_nb - es)
+ *  - velocity update: u' = us, v' = vs.
+ *  - Per-step folds: V_disp = dx dy sum_wet eta', V_tot = dx dy sum_wet (H + eta'),
+ *    max|u'|, max|v'|. The paper's compiler turns loop nests into maps and
+ *    these reductions into folds (Sect. 4.3).
+ *
+ * Plain loops, one full-size array per intermediate, no blocking or fusion.
+ * Rows are independent in every stage, so OpenMP over rows changes no result.
+ * Build: gcc -O3 -march=native -fopenmp -ffp-contract=off (no fast-math).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define AT(a, j, i) ((a)[(size_t)(j) * (size_t)nx + (size_t)(i)])
+
+static int is_wet(const unsigned char *mask, int nx, int ny, int j, int i) {
+    if (i < 0 || j < 0 || i >= nx || j >= ny) return 0;
+    return AT(mask, j, i) != 0;
+}
+
+/* One step. scratch holds 3*nx*ny doubles (Fx, Fy, es). Returns 0, or 1 if a
+ * water cell has non-positive total depth H + eta (the model has no drying). */
+int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, double eps,
+                     const double *H, const unsigned char *mask,
+                     const double *eta, const double *u, const double *v,
+                     double *eta_out, double *u_out, double *v_out,
+                     double *scratch, int nthreads) {
+    const double cx = g * dt / dx, cy = g * dt / dy;
+    const double rx = dt / dx, ry = dt / dy;
+    const double e4 = eps / 4.0;
+    double *Fx = scratch;
+    double *Fy = scratch + (size_t)nx * ny;
+    double *es = scratch + 2 * (size_t)nx * ny;
+    int dry = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+    /* dyn, part 1: predicted face velocities; then the upwinded face fluxes. */
+#pragma omp parallel for schedule(static) reduction(| : dry)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            int w = is_wet(mask, nx, ny, j, i);
+            if (w && !(AT(H, j, i) + AT(eta, j, i) > 0.0)) dry = 1;
+            int au = w && is_wet(mask, nx, ny, j, i + 1);
+            int av = w && is_wet(mask, nx, ny, j + 1, i);
+            double us = 0.0, vs = 0.0, fx = 0.0, fy = 0.0;
+            if (au) {
+                us = AT(u, j, i) - cx * (AT(eta, j, i + 1) - AT(eta, j, i));
+                double h_up = us > 0.0 ? AT(H, j, i) + AT(eta, j, i)
+                                       : AT(H, j, i + 1) + AT(eta, j, i + 1);
+                fx = us * h_up;
+            }
+            if (av) {
+                vs = AT(v, j, i) - cy * (AT(eta, j + 1, i) - AT(eta, j, i));
+                double h_up = vs > 0.0 ? AT(H, j, i) + AT(eta, j, i)
+                                       : AT(H, j + 1, i) + AT(eta, j + 1, i);
+                fy = vs * h_up;
+            }
+            AT(u_out, j, i) = us;
+            AT(v_out, j, i) = vs;
+            AT(Fx, j, i) = fx;
+            AT(Fy, j, i) = fy;
+        }
+    }
+
+    /* dyn, part 2: free surface from the divergence of the fluxes. */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            double e = 0.0;
+            if (is_wet(mask, nx, ny, j, i)) {
+                double fw = i > 0 ? AT(Fx, j, i - 1) : 0.0;
+                double fs = j > 0 ? AT(Fy, j - 1, i) : 0.0;
+                e = AT(eta, j, i) - rx * (AT(Fx, j, i) - fw) - ry * (AT(Fy, j, i) - fs);
+            }
+            AT(es, j, i) = e;
+        }
+    }
+
+    /* shapiro: five-point smoothing that only exchanges across water neighbours. */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            double out = 0.0;
+            if (is_wet(mask, nx, ny, j, i)) {
+                double c = AT(es, j, i);
+                double s = 0.0;
+                if (is_wet(mask, nx, ny, j, i + 1)) s += AT(es, j, i + 1) - c;
+                if (is_wet(mask, nx, ny, j, i - 1)) s += AT(es, j, i - 1) - c;
+                if (is_wet(mask, nx, ny, j + 1, i)) s += AT(es, j + 1, i) - c;
+                if (is_wet(mask, nx, ny, j - 1, i)) s += AT(es, j - 1, i) - c;
+                out = c + e4 * s;
+            }
+            AT(eta_out, j, i) = out;
+        }
+    }
+    return dry;
+}
+
+/* Folds over one state: out[0] = V_tot, out[1] = V_disp, out[2] = max|u|, out[3] = max|v|.
+ * Sums run row by row; the row sums are then added in row order, so the result does
+ * not depend on the thread count. rowbuf holds 2*ny doubles. */
+void sw2d_oracle_reduce(int nx, int ny, double dx, double dy, const double *H,
+                        const unsigned char *mask, const double *eta, const double *u,
+                        const double *v, double *out, double *rowbuf) {
+    double *row_tot = rowbuf, *row_disp = rowbuf + ny;
+    double mu = 0.0, mv = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : mu, mv)
+    for (int j = 0; j < ny; ++j) {
+        double st = 0.0, sd = 0.0;
+        for (int i = 0; i < nx; ++i) {
+            if (AT(mask, j, i)) {
+                st += AT(H, j, i) + AT(eta, j, i);
+                sd += AT(eta, j, i);
+            }
+            double au = fabs(AT(u, j, i)), av = fabs(AT(v, j, i));
+            if (au > mu) mu = au;
+            if (av > mv) mv = av;
+        }
+        row_tot[j] = st;
+        row_disp[j] = sd;
+    }
+    double st = 0.0, sd = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        st += row_tot[j];
+        sd += row_disp[j];
+    }
+    out[0] = dx * dy * st;
+    out[1] = dx * dy * sd;
+    out[2] = mu;
+    out[3] = mv;
+}
+
+/* nsteps steps in place on (eta, u, v). red, if not NULL, receives 4 doubles per step
+ * (the folds of the state after that step). Returns 0, 1 if a water cell dried, or
+ * 2 if memory ran out. */
+int sw2d_oracle_run(int nx, int ny, double dx, double dy, double g, double dt, double eps,
+                    const double *H, const unsigned char *mask,
+                    double *eta, double *u, double *v, int nsteps, double *red, int nthreads) {
+    size_t n = (size_t)nx * ny;
+    double *buf = (double *)malloc(sizeof(double) * (6 * n + 2 * (size_t)ny));
+    if (!buf) return 2;
+    double *e2 = buf, *u2 = buf + n, *v2 = buf + 2 * n, *scratch = buf + 3 * n;
+    double *rowbuf = buf + 6 * n;
+    double *ce = eta, *cu = u, *cv = v, *ne = e2, *nu = u2, *nv = v2;
+    int rc = 0;
+    for (int s = 0; s < nsteps && rc == 0; ++s) {
+        rc = sw2d_oracle_step(nx, ny, dx, dy, g, dt, eps, H, mask, ce, cu, cv, ne, nu, nv,
+                              scratch, nthreads);
+        if (red) sw2d_oracle_reduce(nx, ny, dx, dy, H, mask, ne, nu, nv, red + 4 * (size_t)s, rowbuf);
+        double *t;
+        t = ce; ce = ne; ne = t;
+        t = cu; cu = nu; nu = t;
+        t = cv; cv = nv; nv = t;
+    }
+    if (ce != eta) {
+        memcpy(eta, ce, sizeof(double) * n);
+        memcpy(u, cu, sizeof(double) * n);
+        memcpy(v, cv, sizeof(double) * n);
+    }
+    free(buf);
+    return rc;
+}
+
+int sw2d_oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

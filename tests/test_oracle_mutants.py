@@ -1,0 +1,89 @@
+"""Plant plausible mistakes in a copy of the C oracle and check that the pins catch each.
+
+Every mutant is compiled from the oracle source with one textual change and must
+fail at least one of: the hand-derived two-cell steps, the closed-form mode
+amplification, exact rational arithmetic on tiny grids, or volume conservation.
+"""
+import json
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import build as obuild
+from oracle import exact, sw2d_ref
+from paper_1711_04471_amd import inputs
+
+HERE = os.path.dirname(__file__)
+SRC = os.path.join(os.path.dirname(HERE), "oracle", "sw2d_oracle.c")
+
+MUTANTS = {
+    "upwind_flipped": ("us > 0.0 ? AT(H, j, i) + AT(eta, j, i)", "us < 0.0 ? AT(H, j, i) + AT(eta, j, i)"),
+    "eta_from_old_velocity": ("fx = us * h_up;", "fx = AT(u, j, i) * h_up;"),
+    "pressure_gradient_sign": ("us = AT(u, j, i) - cx *", "us = AT(u, j, i) + cx *"),
+    "dx_for_dy_in_v_predictor": ("vs = AT(v, j, i) - cy *", "vs = AT(v, j, i) - cx *"),
+    "west_flux_index": ("double fw = i > 0 ? AT(Fx, j, i - 1) : 0.0;", "double fw = i > 0 ? AT(Fx, j, i) : 0.0;"),
+    "south_flux_dropped": ("- ry * (AT(Fy, j, i) - fs)", "- ry * AT(Fy, j, i)"),
+    "shapiro_drops_north": ("if (is_wet(mask, nx, ny, j + 1, i)) s += AT(es, j + 1, i) - c;", ""),
+    "shapiro_over_land": ("if (is_wet(mask, nx, ny, j, i - 1)) s += AT(es, j, i - 1) - c;", "s += AT(es, j, i - 1) - c;"),
+    "shapiro_eps_over_2": ("const double e4 = eps / 4.0;", "const double e4 = eps / 2.0;"),
+    "depth_from_new_side": ("AT(H, j + 1, i) + AT(eta, j + 1, i);", "AT(H, j, i) + AT(eta, j + 1, i);"),
+    "volume_counts_land": ("if (AT(mask, j, i)) {", "{"),
+}
+
+
+def _build_mutant(tmp_path, name, find, repl):
+    src = open(SRC).read()
+    assert src.count(find) == 1, f"{name}: pattern must occur exactly once"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(find, repl))
+    lib = tmp_path / f"lib_{name}.so"
+    subprocess.run(["gcc", *obuild.CFLAGS, str(path), "-o", str(lib), "-lm"], check=True)
+    return str(lib)
+
+
+def _pin_golden():
+    cases = json.load(open(os.path.join(HERE, "golden", "two_cell.json")))["cases"]
+    from tests.test_oracle_exact import test_hand_derived_two_cell_steps
+    for c in cases:
+        test_hand_derived_two_cell_steps(c)
+
+
+def _pin_modes():
+    from tests.test_oracle_modes import test_mode_amplification_matches_closed_form
+    test_mode_amplification_matches_closed_form()
+
+
+def _pin_exact():
+    rng = np.random.Generator(np.random.PCG64(77))
+    from tests.test_oracle_exact import _compare
+    for _ in range(6):
+        m = (rng.uniform(size=(3, 4)) < 0.8).astype(np.uint8)
+        _compare(rng, 6, 5, m, steps=3)
+
+
+def _pin_volume():
+    from tests.test_oracle_invariants import test_volume_is_conserved_in_a_closed_basin
+    test_volume_is_conserved_in_a_closed_basin()
+
+
+PINS = (_pin_golden, _pin_modes, _pin_exact, _pin_volume)
+
+
+def test_unmutated_oracle_passes_every_pin():
+    for pin in PINS:
+        pin()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_each_planted_mistake_is_caught(tmp_path, name):
+    lib = _build_mutant(tmp_path, name, *MUTANTS[name])
+    caught = []
+    with sw2d_ref.library(lib):
+        for pin in PINS:
+            try:
+                pin()
+            except (AssertionError, sw2d_ref.DryCellError):
+                caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every pin"
