@@ -1,0 +1,116 @@
+"""Benchmark of the fused 2DSW step on one MI355X.
+
+One benchmark step = one model time step (predictor, flux-divergence surface update,
+Shapiro filter, velocity update and the per-step folds) of the 8192 x 8192 basin
+(dx = 250 m, seeded bathymetry, land disks and 8 bumps), with the state resident in HBM.
+value = nx * ny * steps / wall time, in Mcell-steps/s. The roofline object prices the
+step kernel at its algorithmic 28 B per cell-step (read eta, u, v, H; write eta, u, v)
+against MI355X's 8 TB/s, using the mean step-kernel duration from HIP events recorded
+on the library's stream inside the timed region. cpu_baseline times the FP64 oracle on
+the host cores over a bounded number of steps of the same basin.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_CELL_STEP = 28
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="basin_8192", choices=["basin_8192", "basin_2048"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--band-rows", type=int, default=0)
+    return ap.parse_args()
+
+
+def cpu_baseline(case, target_s):
+    """The FP64 oracle on the host cores: 1 probe step, then enough steps for ~target_s."""
+    from oracle import sw2d_ref
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    sw2d_ref.run_case(case, nsteps=1, nthreads=threads)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(case.steps, int(target_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    sw2d_ref.run_case(case, nsteps=n, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": case.nx * case.ny * n / dt / 1e6, "unit": "Mcell-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{case.name} full grid, {n} steps with folds, FP64, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(row-strip sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1711_04471_amd import inputs
+    from paper_1711_04471_amd.sw2d import Sw2d
+
+    case = inputs.basin_8192() if args.workload == "basin_8192" else inputs.basin_2048()
+    dev = torch.device("cuda:0")
+    sim = Sw2d.from_case(case, device=dev)
+    if args.band_rows:
+        sim.band_rows = args.band_rows
+    print(f"# {case.name} {case.nx}x{case.ny} band_rows={sim.band_rows} warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    red = sim.reduce(min(args.steps, 16))
+    # the same number of steps again with an event pair around every step kernel
+    kernel_ms = sim.step_timed(args.steps)
+    cells = case.nx * case.ny
+    value = cells * args.steps / wall / 1e6
+    achieved = cells * BYTES_PER_CELL_STEP / (kernel_ms * 1e-3) / 1e9
+    out = {
+        "metric": "Mcell-steps/s and % HBM roofline (plain vs surrogate/batched at stated RMSE)",
+        "value": round(value, 1),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{case.name}: {case.nx}x{case.ny} cells incl. land border, "
+                               f"dx={case.dx:g} m, dt={case.dt:.4f} s, eps={case.eps}, seeded "
+                               "Fourier bathymetry 5-50 m, land disks >=10%, 8 bumps",
+                   "nx": case.nx, "ny": case.ny, "band_rows": sim.band_rows},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "sw2d_step_kernel", "kernel_ms": round(kernel_ms, 5),
+                     "bytes_per_cell_step": BYTES_PER_CELL_STEP},
+        "folds_last_step": {"vol_total": float(red["vol_total"][-1]),
+                            "vol_disp": float(red["vol_disp"][-1]),
+                            "max_abs_u": float(red["max_abs_u"][-1]),
+                            "max_abs_v": float(red["max_abs_v"][-1])},
+    }
+    sim.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,135 @@
+/*
+ * sw2d.h - C ABI of the MI355X (gfx950) 2-D shallow-water (2DSW) step library.
+ *
+ * The model is the one of the paper's first auto-parallelisation test case
+ * (Sect. 6.2, "Test Case 1: 2-D Shallow Water Model"): a time loop that calls a
+ * predictor ("dyn"), then a first-order Shapiro filter ("shapiro"), then updates
+ * the velocity; the paper's compiler turns its loop nests into maps and its
+ * reductions into folds (Sect. 4.3) and keeps the data on the accelerator for the
+ * whole run, copying only once (Sect. 4.3, last paragraph). The paper prints no
+ * equations; this library implements the standard explicit Arakawa C-grid reading:
+ *
+ *   us  = a_u (u - g dt/dx (eta_E - eta))            a_u: both cells of the face wet
+ *   vs  = a_v (v - g dt/dy (eta_N - eta))
+ *   Fx  = us * (us > 0 ? H + eta : H_E + eta_E)        upwind total depth, old surface
+ *   es  = wet (eta - dt/dx (Fx - Fx_W) - dt/dy (Fy - Fy_S))
+ *   eta'= wet (es + eps/4 * sum over wet neighbours (es_nb - es))
+ *   u'  = us, v' = vs
+ *
+ * and after every step the folds V_tot = dx dy sum_wet (H + eta'),
+ * V_disp = dx dy sum_wet eta' (both accumulated in double), max|u'| and max|v'|.
+ *
+ * Layout: every field is a row-major [ny][nx] float32 array (i runs east along a
+ * row, j runs north). u[j][i] sits on the east face of cell (j,i), v[j][i] on its
+ * north face, so u[.][nx-1] and v[ny-1][.] are always zero. mask[j][i] != 0 means
+ * water. The outermost ring of cells must be land (closed basin).
+ *
+ * Ownership: the caller owns every device buffer (state, depth, mask, workspace)
+ * and the HIP stream; they must outlive the handle. The library owns only its
+ * host-side handle and never allocates device memory.
+ *
+ * Errors: every call returns an int status (SW2D_OK or a negative code below);
+ * nothing throws or aborts across the ABI. Work is enqueued asynchronously on the
+ * caller's stream; an asynchronous HIP error surfaces at a later call or at
+ * sw2d_reduce, which synchronises the stream. A handle is not thread-safe.
+ */
+#ifndef SW2D_H
+#define SW2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SW2D_OK = 0,
+    SW2D_EINVAL = -1,    /* bad sizes/constants, wet border cell, bad depth, CFL > 1 */
+    SW2D_EHIP = -2,      /* a HIP runtime call failed; see sw2d_strerror / sw2d_last_hip_error */
+    SW2D_EUNSTABLE = -3, /* a fold came back non-finite: the run has blown up */
+    SW2D_ESTATE = -4,    /* handle misuse (NULL handle, bad k, ...) */
+    SW2D_ENOSPC = -5     /* workspace smaller than sw2d_workspace_bytes() */
+};
+
+/* Grid and constants. nx, ny count every cell, land border included (>= 3 each).
+ * dx, dy, dt > 0 and finite; g >= 0 and finite; eps in [0, 1] (Shapiro weight).
+ * flags is reserved and must be 0. */
+typedef struct {
+    int32_t nx, ny;
+    double dx, dy, g, dt, eps;
+    uint32_t flags;
+} sw2d_params;
+
+/* The folds of the state after one step (32 bytes; the device writes this layout). */
+typedef struct {
+    int64_t step;      /* 1-based index of the step this entry follows */
+    double vol_total;  /* dx dy sum_wet (H + eta) [m^3] */
+    double vol_disp;   /* dx dy sum_wet eta        [m^3] */
+    float max_abs_u;   /* max over all faces of |u| [m/s] */
+    float max_abs_v;   /* max over all faces of |v| [m/s] */
+} sw2d_red;
+
+typedef struct sw2d_ctx *sw2d_t;
+
+/* Device workspace (bytes) a handle needs for these params: the packed depth field,
+ * per-workgroup fold partials, the fold ring and a few flags. 0 if params are bad. */
+size_t sw2d_workspace_bytes(const sw2d_params *p);
+
+/* Number of past steps whose folds sw2d_reduce can still return. */
+int32_t sw2d_ring_capacity(void);
+
+/* Validate and bind a problem. d_H (float32 [ny][nx], depth below the rest level,
+ * ignored on land), d_mask (uint8 [ny][nx]) are read once; d_state holds 6*nx*ny
+ * float32 = two (eta, u, v) buffers, buffer 0 holding the initial state; d_work is
+ * the workspace. Checks (SW2D_EINVAL): sizes/constants; border cells must be land;
+ * water cells need finite H > 0 and H + eta > 0; the initial state must be finite;
+ * the Courant number dt sqrt(g H_max) sqrt(1/dx^2 + 1/dy^2) must not exceed 1.
+ * Synchronises the stream once. On success *out is a new handle. */
+int sw2d_create(const sw2d_params *p, const float *d_H, const uint8_t *d_mask, float *d_state,
+                void *d_work, size_t work_bytes, void *hip_stream, sw2d_t *out);
+
+/* Enqueue nsteps >= 0 time steps (and their folds) on the handle's stream. No host
+ * synchronisation, no host-device copy. */
+int sw2d_step(sw2d_t h, int32_t nsteps);
+
+/* Benchmark form of sw2d_step: the same launches, with a HIP event pair recorded on the
+ * handle's stream around every step kernel. Synchronises the stream and writes the mean
+ * duration of one step kernel in milliseconds to *mean_step_ms. */
+int sw2d_step_timed(sw2d_t h, int32_t nsteps, double *mean_step_ms);
+
+/* Copy the folds of the last k steps (oldest first) into host_out[0..k-1]; k must be
+ * in [1, min(steps done, sw2d_ring_capacity())]. Synchronises the stream. Returns
+ * SW2D_EUNSTABLE (entries still written) when any returned fold is non-finite. */
+int sw2d_reduce(sw2d_t h, sw2d_red *host_out, int32_t k);
+
+/* Device pointers of the current (eta, u, v) buffers inside d_state. Valid until the
+ * next sw2d_step / sw2d_set_state on this handle. */
+int sw2d_state(sw2d_t h, float **d_eta, float **d_u, float **d_v);
+
+/* Steps done so far (the restart counter). */
+int64_t sw2d_steps_done(sw2d_t h);
+
+/* Overwrite the current state with device arrays (float32 [ny][nx] each; they may be
+ * the current buffers themselves) and set the step counter. Enqueued on the stream. */
+int sw2d_set_state(sw2d_t h, const float *d_eta, const float *d_u, const float *d_v, int64_t step);
+
+/* Band height (rows per workgroup) of the fused step. Any value in [8, ny] gives the same
+ * state bit for bit; it changes speed, and the grouping (not the value) of fold sums. */
+int sw2d_set_band_rows(sw2d_t h, int32_t rows);
+int32_t sw2d_band_rows(sw2d_t h);
+
+/* Release the host handle. Device buffers stay the caller's. NULL is accepted. */
+int sw2d_destroy(sw2d_t h);
+
+/* Static text for a status code. */
+const char *sw2d_strerror(int code);
+
+/* Text of the last HIP error seen by this library on the calling thread ("" if none). */
+const char *sw2d_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SW2D_H */

@@ -1,0 +1,82 @@
+// sw2d_internal.h - types shared by the 2DSW kernels and the C ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw2d.h"
+
+namespace sw2d {
+
+constexpr int kWave = 64;                            // CDNA wavefront width
+constexpr int kHalo = 2;                             // stencil radius of the fused step
+constexpr int kStripOut = kWave - 2 * kHalo;         // output columns per wave strip (60)
+constexpr int kWavesPerGroup = 4;                    // strips per workgroup
+constexpr int kGroupThreads = kWave * kWavesPerGroup;
+constexpr int kGroupCols = kStripOut * kWavesPerGroup;  // 240 output columns per workgroup
+constexpr int kFoldThreads = 256;
+constexpr int kXcds = 8;                             // MI355X: 8 XCDs, one L2 each
+constexpr int kMinRows = 8;                          // smallest band height a handle may use
+constexpr int kFoldChunk = 16;                       // steps whose partials are buffered
+constexpr int kRingCap = 4096;                       // steps of folds kept for sw2d_reduce
+
+// Per-workgroup fold partial of one step (32 B).
+struct alignas(32) FoldPartial {
+    double tot;   // sum over water cells of H + eta
+    double disp;  // sum over water cells of eta
+    float mu;     // max |u|
+    float mv;     // max |v|
+    float pad[2];
+};
+
+struct StepGeometry {
+    int nx, ny;
+    int strips;    // ceil(nx / kStripOut)
+    int groups_x;  // ceil(strips / kWavesPerGroup)
+    int rows;      // rows per band
+    int bands;     // ceil(ny / rows)
+    int nblocks;   // groups_x * bands
+};
+
+// Step coefficients, computed in double on the host and rounded once to float.
+struct StepCoef {
+    float cx, cy;  // g dt / dx, g dt / dy
+    float rx, ry;  // dt / dx, dt / dy
+    float e4;      // eps / 4
+};
+
+enum : uint32_t {
+    kWetBorder = 1u,
+    kBadDepth = 2u,
+    kBadState = 4u,
+    kDryCell = 8u,
+};
+
+struct PrepFlags {
+    uint32_t bad;        // OR of the k* bits above
+    uint32_t hmax_bits;  // bit pattern of the largest water depth (positive float)
+};
+
+inline StepGeometry make_geometry(int nx, int ny, int rows) {
+    StepGeometry g;
+    g.nx = nx;
+    g.ny = ny;
+    g.strips = (nx + kStripOut - 1) / kStripOut;
+    g.groups_x = (g.strips + kWavesPerGroup - 1) / kWavesPerGroup;
+    g.rows = rows;
+    g.bands = (ny + rows - 1) / rows;
+    g.nblocks = g.groups_x * g.bands;
+    return g;
+}
+
+hipError_t launch_step(const float* eta, const float* u, const float* v, const float* hp,
+                       float* eta_o, float* u_o, float* v_o, FoldPartial* part,
+                       const StepGeometry& geo, const StepCoef& k, hipStream_t s);
+// Partials of step s of the chunk start at part + s * stride; nparts of them are valid.
+hipError_t launch_fold(const FoldPartial* part, int nparts, int stride, int nsteps,
+                       int64_t first_step, sw2d_red* ring, int ring_cap, double cell_area,
+                       hipStream_t s);
+hipError_t launch_prep(const float* H, const uint8_t* mask, const float* eta, const float* u,
+                       const float* v, int nx, int ny, float* hp, PrepFlags* flags, hipStream_t s);
+
+}  // namespace sw2d

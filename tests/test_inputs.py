@@ -1,0 +1,38 @@
+"""The seeded input recipe: ranges, land fraction, determinism (host logic only)."""
+import numpy as np
+
+from paper_1711_04471_amd import inputs
+
+
+def test_seeded_basin_recipe():
+    c = inputs.small_basin(300, 220, seed=3)
+    wet = c.mask != 0
+    assert not wet[0].any() and not wet[-1].any() and not wet[:, 0].any() and not wet[:, -1].any()
+    interior = wet[1:-1, 1:-1]
+    assert 1.0 - interior.mean() >= 0.10
+    assert 5.0 - 1e-5 <= c.H.min() and c.H.max() <= 50.0 + 1e-5
+    assert c.eta.dtype == np.float32 and not c.eta[~wet].any()
+    assert 0 < c.eta.max() <= 3.5
+    assert c.dt == inputs.stable_dt(c.dx, c.dy, c.g, float(c.H[wet].max()))
+
+
+def test_same_seed_same_arrays():
+    a, b = inputs.small_basin(90, 70, seed=5), inputs.small_basin(90, 70, seed=5)
+    for x, y in ((a.H, b.H), (a.mask, b.mask), (a.eta, b.eta)):
+        assert np.array_equal(x, y)
+    c = inputs.small_basin(90, 70, seed=6)
+    assert not np.array_equal(a.eta, c.eta)
+
+
+def test_gaussian_basin_64():
+    c = inputs.gaussian_basin_64()
+    assert (c.nx, c.ny, c.steps) == (66, 66, 200)
+    assert c.eta.max() > 0.98 and abs(c.dt - 0.5 * 100 / np.sqrt(98.1)) < 1e-12
+    # the bump is centred on the corner shared by cells 32 and 33: symmetric
+    assert np.array_equal(c.eta[:, 1:-1], c.eta[:, -2:0:-1])
+
+
+def test_ensemble_sizes():
+    s = inputs.ensemble_sizes()
+    assert len(s) == 256 and all(128 <= a <= 1024 and 128 <= b <= 1024 for a, b in s)
+    assert s == inputs.ensemble_sizes()
