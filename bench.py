@@ -31,17 +31,44 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--band-rows", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain 1 GiB device-to-device copy (the counter calibration)")
     return ap.parse_args()
 
 
+def copy_probe():
+    """A plain device copy of known size: 1 GiB read + 1 GiB written per launch."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"probe": "device copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "ms": round(ms, 4), "GBs": round(8 * n / ms / 1e6, 1)}), flush=True)
+
+
 def cpu_baseline(case, target_s):
-    """The FP64 oracle on the host cores: 1 probe step, then enough steps for ~target_s."""
+    """The FP64 oracle on the host cores: probes of 1 and 3 steps give the cost of one step
+    (without the one-off conversion of the inputs), then enough steps for ~target_s."""
     from oracle import sw2d_ref
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     sw2d_ref.run_case(case, nsteps=1, nthreads=threads)
-    t1 = time.perf_counter() - t0
-    n = max(1, min(case.steps, int(target_s / max(t1, 1e-6))))
+    t1 = time.perf_counter()
+    sw2d_ref.run_case(case, nsteps=3, nthreads=threads)
+    t3 = time.perf_counter()
+    per_step = max(((t3 - t1) - (t1 - t0)) / 2.0, 1e-6)
+    n = max(1, min(case.steps, int(target_s / per_step)))
     t0 = time.perf_counter()
     sw2d_ref.run_case(case, nsteps=n, nthreads=threads)
     dt = time.perf_counter() - t0
@@ -52,6 +79,9 @@ def cpu_baseline(case, target_s):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(row-strip sharding is a design note only); run with --gpus 1", file=sys.stderr)

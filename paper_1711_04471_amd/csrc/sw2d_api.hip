@@ -30,6 +30,7 @@ struct sw2d_ctx {
     int64_t step;             // steps done
     int64_t ring_first;       // first step whose fold is valid in the ring
     double h_max;
+    double h_sum;  // sum over water cells of H
 };
 
 namespace {
@@ -82,17 +83,19 @@ Layout layout(const sw2d_params* p) {
     L.ring = off;
     off = align_up(off + (size_t)kRingCap * sizeof(sw2d_red));
     L.part = off;
-    off = align_up(off + (size_t)kFoldChunk * L.part_capacity * sizeof(FoldPartial));
+    size_t part_bytes = (size_t)kFoldChunk * L.part_capacity * sizeof(FoldPartial);
+    if (part_bytes < kHsumBlocks * sizeof(double)) part_bytes = kHsumBlocks * sizeof(double);
+    off = align_up(off + part_bytes);
     L.total = off;
     return L;
 }
 
 int default_rows(int nx, int ny) {
-    // Tall bands amortise the 4 halo rows each band re-reads; keep enough workgroups
-    // (>= 8 per CU on 256 CUs) to fill the chip.
-    for (int rows = 64; rows > kMinRows; rows /= 2) {
-        if (make_geometry(nx, ny, rows).nblocks >= 2048) return rows;
-    }
+    // Measured on the 8192^2 basin: short bands keep the rows in flight close together
+    // in HBM, which matters more than the 4 halo rows each band re-reads; 16 rows is the
+    // tuned height. Small grids drop to the minimum to keep >= 8 workgroups per CU.
+    const int rows = 16;
+    if (make_geometry(nx, ny, rows).nblocks >= 2048 || ny <= rows) return rows < ny ? rows : ny;
     return kMinRows;
 }
 
@@ -109,7 +112,7 @@ StepCoef make_coef(const sw2d_params* p) {
 int flush_folds(sw2d_ctx* h, int pending) {
     if (pending <= 0) return SW2D_OK;
     SW2D_HIP(launch_fold(h->part, h->geo.nblocks, h->part_capacity, pending, h->step - pending + 1,
-                         h->ring, kRingCap, h->p.dx * h->p.dy, h->stream));
+                         h->ring, kRingCap, h->p.dx * h->p.dy, h->h_sum, h->stream));
     return SW2D_OK;
 }
 
@@ -152,12 +155,12 @@ int sw2d_create(const sw2d_params* p, const float* d_H, const uint8_t* d_mask, f
     h->step = 0;
     h->ring_first = 1;
 
-    PrepFlags host_flags{0u, 0u};
+    PrepFlags host_flags{0u, 0u, 0.0};
     hipError_t e = hipMemcpyAsync(h->flags, &host_flags, sizeof host_flags, hipMemcpyHostToDevice,
                                   h->stream);
     if (e == hipSuccess)
         e = launch_prep(d_H, d_mask, h->state[0][0], h->state[0][1], h->state[0][2], p->nx, p->ny,
-                        h->hp, h->flags, h->stream);
+                        h->hp, h->flags, reinterpret_cast<double*>(h->part), h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&host_flags, h->flags, sizeof host_flags, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -172,6 +175,7 @@ int sw2d_create(const sw2d_params* p, const float* d_H, const uint8_t* d_mask, f
     float hmax;
     std::memcpy(&hmax, &host_flags.hmax_bits, sizeof hmax);
     h->h_max = hmax;
+    h->h_sum = host_flags.h_sum;
     const double courant =
         p->dt * std::sqrt(p->g * h->h_max) * std::sqrt(1.0 / (p->dx * p->dx) + 1.0 / (p->dy * p->dy));
     if (!(courant <= 1.0)) {

@@ -11,7 +11,10 @@ namespace sw2d {
 constexpr int kWave = 64;                            // CDNA wavefront width
 constexpr int kHalo = 2;                             // stencil radius of the fused step
 constexpr int kStripOut = kWave - 2 * kHalo;         // output columns per wave strip (60)
-constexpr int kWavesPerGroup = 4;                    // strips per workgroup
+#ifndef SW2D_WAVES_PER_GROUP
+#define SW2D_WAVES_PER_GROUP 4
+#endif
+constexpr int kWavesPerGroup = SW2D_WAVES_PER_GROUP;  // strips per workgroup
 constexpr int kGroupThreads = kWave * kWavesPerGroup;
 constexpr int kGroupCols = kStripOut * kWavesPerGroup;  // 240 output columns per workgroup
 constexpr int kFoldThreads = 256;
@@ -20,13 +23,11 @@ constexpr int kMinRows = 8;                          // smallest band height a h
 constexpr int kFoldChunk = 16;                       // steps whose partials are buffered
 constexpr int kRingCap = 4096;                       // steps of folds kept for sw2d_reduce
 
-// Per-workgroup fold partial of one step (32 B).
-struct alignas(32) FoldPartial {
-    double tot;   // sum over water cells of H + eta
+// Per-workgroup fold partial of one step (16 B).
+struct alignas(16) FoldPartial {
     double disp;  // sum over water cells of eta
     float mu;     // max |u|
     float mv;     // max |v|
-    float pad[2];
 };
 
 struct StepGeometry {
@@ -55,7 +56,10 @@ enum : uint32_t {
 struct PrepFlags {
     uint32_t bad;        // OR of the k* bits above
     uint32_t hmax_bits;  // bit pattern of the largest water depth (positive float)
+    double h_sum;        // sum over water cells of H (static part of the total volume)
 };
+
+constexpr int kHsumBlocks = 256;  // partials of the one-off sum_wet H
 
 inline StepGeometry make_geometry(int nx, int ny, int rows) {
     StepGeometry g;
@@ -75,8 +79,10 @@ hipError_t launch_step(const float* eta, const float* u, const float* v, const f
 // Partials of step s of the chunk start at part + s * stride; nparts of them are valid.
 hipError_t launch_fold(const FoldPartial* part, int nparts, int stride, int nsteps,
                        int64_t first_step, sw2d_red* ring, int ring_cap, double cell_area,
-                       hipStream_t s);
+                       double h_sum, hipStream_t s);
+// Validation + packing, then sum_wet H; scratch holds kHsumBlocks doubles.
 hipError_t launch_prep(const float* H, const uint8_t* mask, const float* eta, const float* u,
-                       const float* v, int nx, int ny, float* hp, PrepFlags* flags, hipStream_t s);
+                       const float* v, int nx, int ny, float* hp, PrepFlags* flags,
+                       double* scratch, hipStream_t s);
 
 }  // namespace sw2d
