@@ -128,6 +128,66 @@ const char *sw2d_strerror(int code);
 /* Text of the last HIP error seen by this library on the calling thread ("" if none). */
 const char *sw2d_last_hip_error(void);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched ensembles: n independent basins of any sizes advanced together by one
+ * persistent launch per chunk of steps (a grid barrier between steps), the launch
+ * sequence recorded once in a HIP graph and replayed. Each instance runs the same tile
+ * routine as sw2d_step, so its state is bitwise equal to the same basin stepped alone;
+ * its folds are equal up to the order of the sums. This is the same time loop
+ * (Sect. 6.2) applied to many problems at once; the paper itself runs one grid at a time.
+ * ------------------------------------------------------------------------------------ */
+typedef struct sw2d_bctx *sw2d_batch_t;
+
+/* Workspace bytes for n instances with params p[0..n-1] and band heights band_rows
+ * (rows per work item, >= 8, one per instance; NULL = 16). 0 if any argument is bad. */
+size_t sw2d_batch_workspace_bytes(int32_t n, const sw2d_params *p, const int32_t *band_rows);
+
+/* Validate and bind n instances. Instance i has its own d_H[i], d_mask[i] and d_state[i]
+ * (6*nx*ny float32: two (eta, u, v) buffers, buffer 0 holding its initial state), all laid
+ * out as for sw2d_create and checked the same way (SW2D_EINVAL names no instance; the
+ * caller can create instances alone to find it). Arrays of pointers are read during the
+ * call only. Synchronises the stream. The library creates one private HIP stream per
+ * handle, used only to record graphs. */
+int sw2d_batch_create(int32_t n, const sw2d_params *p, const float *const *d_H,
+                      const uint8_t *const *d_mask, float *const *d_state, const int32_t *band_rows,
+                      void *d_work, size_t work_bytes, void *hip_stream, sw2d_batch_t *out);
+
+/* Launch shape: steps per persistent launch (>= 1, default 50), whether sw2d_batch_step
+ * records and replays a HIP graph (default 1), and the persistent grid size in
+ * workgroups (0 = the most the device holds at once; larger values are rejected so the
+ * grid barrier always has every workgroup resident). Drops any recorded graph. */
+int sw2d_batch_set_launch(sw2d_batch_t b, int32_t steps_per_launch, int32_t use_graph, int32_t grid);
+
+/* Enqueue nsteps steps of every instance on the stream (no host synchronisation). With
+ * graphs on, the first call for a given nsteps records the graph; later calls with the
+ * same nsteps replay it. */
+int sw2d_batch_step(sw2d_batch_t b, int32_t nsteps);
+
+/* sw2d_batch_step bracketed by HIP events on the stream; synchronises and writes the mean
+ * wall time per step (ms) of the whole enqueued sequence. */
+int sw2d_batch_step_timed(sw2d_batch_t b, int32_t nsteps, double *ms_per_step);
+
+/* Folds of the last step of every instance into host_out[0..n-1]. Synchronises. Returns
+ * SW2D_EHIP if a grid-barrier wait ran past its 2 s deadline (the kernel then stopped
+ * early), SW2D_EUNSTABLE if a fold is non-finite. */
+int sw2d_batch_reduce(sw2d_batch_t b, sw2d_red *host_out);
+
+/* Current (eta, u, v) device buffers of instance k. */
+int sw2d_batch_state(sw2d_batch_t b, int32_t k, float **d_eta, float **d_u, float **d_v);
+
+int64_t sw2d_batch_steps_done(sw2d_batch_t b);
+
+/* Deadline of one grid-barrier wait (default 2 s, at most 60 s). A wait past it sets the
+ * error that sw2d_batch_reduce reports and makes every workgroup return; the tests use a
+ * zero deadline to exercise that path. Drops any recorded graph. */
+int sw2d_batch_set_barrier_timeout(sw2d_batch_t b, double seconds);
+
+/* Persistent grid size in workgroups (256 threads each). */
+int32_t sw2d_batch_grid(sw2d_batch_t b);
+
+/* Release the handle, its graph and its private stream. NULL is accepted. */
+int sw2d_batch_destroy(sw2d_batch_t b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,20 @@ SIGNATURES = {
     "sw2d_band_rows": (ctypes.c_int32, [_vp]),
     "sw2d_destroy": (ctypes.c_int, [_vp]),
     "sw2d_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sw2d_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(sw2d_params),
+                                                     ctypes.POINTER(ctypes.c_int32)]),
+    "sw2d_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(sw2d_params), _pp, _pp, _pp,
+                                         ctypes.POINTER(ctypes.c_int32), _vp, ctypes.c_size_t, _vp,
+                                         _pp]),
+    "sw2d_batch_set_launch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "sw2d_batch_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "sw2d_batch_step_timed": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "sw2d_batch_reduce": (ctypes.c_int, [_vp, ctypes.POINTER(sw2d_red)]),
+    "sw2d_batch_state": (ctypes.c_int, [_vp, ctypes.c_int32, _pp, _pp, _pp]),
+    "sw2d_batch_steps_done": (ctypes.c_int64, [_vp]),
+    "sw2d_batch_set_barrier_timeout": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "sw2d_batch_grid": (ctypes.c_int32, [_vp]),
+    "sw2d_batch_destroy": (ctypes.c_int, [_vp]),
     "sw2d_last_hip_error": (ctypes.c_char_p, []),
 }
 

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsw2d.so")
 
-SOURCES = ["sw2d_kernels.hip", "sw2d_api.hip"]
+SOURCES = ["sw2d_kernels.hip", "sw2d_api.hip", "sw2d_batch.hip"]
 
 ARCH = "gfx950"
 HIPFLAGS = [

@@ -118,6 +118,14 @@ int flush_folds(sw2d_ctx* h, int pending) {
 
 }  // namespace
 
+namespace sw2d {
+namespace detail {
+bool params_valid(const sw2d_params* p) { return params_ok(p); }
+StepCoef make_coef(const sw2d_params* p) { return ::make_coef(p); }
+void set_hip_message(const char* msg) { std::snprintf(g_hip_msg, sizeof g_hip_msg, "%s", msg); }
+}  // namespace detail
+}  // namespace sw2d
+
 extern "C" {
 
 size_t sw2d_workspace_bytes(const sw2d_params* p) {

@@ -85,4 +85,11 @@ hipError_t launch_prep(const float* H, const uint8_t* mask, const float* eta, co
                        const float* v, int nx, int ny, float* hp, PrepFlags* flags,
                        double* scratch, hipStream_t s);
 
+namespace detail {
+// Shared by the single-grid and batched C ABI (defined in sw2d_api.hip).
+bool params_valid(const sw2d_params* p);
+StepCoef make_coef(const sw2d_params* p);
+void set_hip_message(const char* msg);
+}  // namespace detail
+
 }  // namespace sw2d

@@ -145,3 +145,113 @@ class Sw2d:
             self.close()
         except Exception:
             pass
+
+
+class Sw2dBatch:
+    """An ensemble of independent basins advanced together (``sw2d_batch_*``).
+
+    ``cases`` is a sequence of ``Case``-like objects (nx, ny, dx, dy, g, dt, eps, H, mask,
+    eta, u, v); ``band_rows`` gives each instance's band height (None = library default).
+    """
+
+    def __init__(self, cases, band_rows=None, device="cuda"):
+        lib = _lib.load()
+        self.device = torch.device(device)
+        self.n = len(cases)
+        self.shapes = [(int(c.ny), int(c.nx)) for c in cases]
+        self.params = (sw2d_params * self.n)(*[params(c.nx, c.ny, c.dx, c.dy, c.g, c.dt, c.eps)
+                                               for c in cases])
+        self.rows = None
+        if band_rows is not None:
+            self.rows = (ctypes.c_int32 * self.n)(*[int(r) for r in band_rows])
+        self.H, self.mask, self.state_buf = [], [], []
+        for c in cases:
+            n = int(c.nx) * int(c.ny)
+            self.H.append(_dev_tensor(c.H, torch.float32, self.device))
+            self.mask.append(_dev_tensor(c.mask, torch.uint8, self.device))
+            st = torch.empty(6 * n, dtype=torch.float32, device=self.device)
+            for f, a in enumerate((c.eta, c.u, c.v)):
+                st[f * n:(f + 1) * n].copy_(_dev_tensor(a, torch.float32, self.device).view(-1))
+            self.state_buf.append(st)
+        wb = lib.sw2d_batch_workspace_bytes(self.n, self.params, self.rows)
+        if wb == 0:
+            raise _lib.Sw2dError(_lib.SW2D_EINVAL, "sw2d_batch_workspace_bytes")
+        self.work = torch.empty(int(wb), dtype=torch.uint8, device=self.device)
+        ptrs = lambda ts: (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in ts])
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(lib.sw2d_batch_create(self.n, self.params, ptrs(self.H), ptrs(self.mask),
+                                    ptrs(self.state_buf), self.rows, self.work.data_ptr(), int(wb),
+                                    self.stream.cuda_stream, ctypes.byref(h)), "sw2d_batch_create")
+        self.h = h
+
+    def _handle(self):
+        if self.h is None:
+            raise _lib.Sw2dError(_lib.SW2D_ESTATE, "use after close")
+        return self.h
+
+    def set_launch(self, steps_per_launch=50, use_graph=True, grid=0):
+        check(_lib.load().sw2d_batch_set_launch(self._handle(), int(steps_per_launch),
+                                                int(bool(use_graph)), int(grid)),
+              "sw2d_batch_set_launch")
+
+    def set_barrier_timeout(self, seconds: float):
+        check(_lib.load().sw2d_batch_set_barrier_timeout(self._handle(), float(seconds)),
+              "sw2d_batch_set_barrier_timeout")
+
+    @property
+    def grid(self) -> int:
+        return int(_lib.load().sw2d_batch_grid(self._handle()))
+
+    @property
+    def steps_done(self) -> int:
+        return int(_lib.load().sw2d_batch_steps_done(self._handle()))
+
+    def step(self, nsteps: int) -> None:
+        check(_lib.load().sw2d_batch_step(self._handle(), int(nsteps)), "sw2d_batch_step")
+
+    def step_timed(self, nsteps: int) -> float:
+        ms = ctypes.c_double()
+        check(_lib.load().sw2d_batch_step_timed(self._handle(), int(nsteps), ctypes.byref(ms)),
+              "sw2d_batch_step_timed")
+        return float(ms.value)
+
+    def reduce(self) -> np.ndarray:
+        out = (sw2d_red * self.n)()
+        check(_lib.load().sw2d_batch_reduce(self._handle(), out), "sw2d_batch_reduce")
+        return np.frombuffer(bytearray(out), dtype=RED_DTYPE).copy()
+
+    def state(self, k: int):
+        pe, pu, pv = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        check(_lib.load().sw2d_batch_state(self._handle(), int(k), ctypes.byref(pe),
+                                           ctypes.byref(pu), ctypes.byref(pv)), "sw2d_batch_state")
+        base = self.state_buf[k].data_ptr()
+        ny, nx = self.shapes[k]
+        n = nx * ny
+        out = []
+        for p in (pe, pu, pv):
+            off = (p.value - base) // 4
+            out.append(self.state_buf[k][off:off + n].view(ny, nx))
+        return tuple(out)
+
+    def state_numpy(self, k: int):
+        torch.cuda.synchronize(self.device)
+        return tuple(t.cpu().numpy().copy() for t in self.state(k))
+
+    def close(self) -> None:
+        if self.h is not None:
+            self.stream.synchronize()
+            _lib.load().sw2d_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
