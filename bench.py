@@ -11,6 +11,8 @@ the host cores over a bounded number of steps of the same basin.
 """
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -31,6 +33,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--band-rows", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--only-batched", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy (the counter calibration)")
     return ap.parse_args()
@@ -77,10 +82,68 @@ def cpu_baseline(case, target_s):
             "sample": f"{case.name} full grid, {n} steps with folds, FP64, {dt:.1f} s"}
 
 
+def batched_leg(steps, warmup, log):
+    """The 256-member ensemble (sides 128..1024, own bathymetry, mask, bumps and dt each)
+    advanced by the persistent batched launch, against the same members stepped one after
+    another through sw2d_step on the same GPU."""
+    import tempfile
+
+    import torch
+
+    from paper_1711_04471_amd import autotune, inputs
+    from paper_1711_04471_amd.sw2d import Sw2d, Sw2dBatch
+
+    cases = inputs.ensemble(steps=steps)
+    cells = sum(c.nx * c.ny for c in cases)
+    cache = os.path.join(tempfile.gettempdir(), "sw2d_autotune.json")
+    rows = autotune.tune(cases, cache_path=cache, log=log)
+    with Sw2dBatch(cases, band_rows=rows) as b:
+        b.step(warmup)
+        b.step(steps)  # records the graph for this step count
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = b.step_timed(steps)
+        grid = b.grid
+        red = b.reduce()
+    # the same members one after another through the single-grid path
+    sims = [Sw2d.from_case(c) for c in cases]
+    for s in sims:
+        s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    achieved = cells * BYTES_PER_CELL_STEP / (ev_ms * 1e-3) / 1e9
+    return {
+        "workload": f"ensemble_256: 256 basins, sides U{{128..1024}} (seed 4), members seed "
+                    f"40000+k, 1-4 bumps, dx=500 m, own dt; {cells} cells in total",
+        "steps": steps, "value": round(cells * steps / wall / 1e6, 1), "unit": "Mcell-steps/s",
+        "ms_per_step": round(wall / steps * 1e3, 5),
+        "sequential_value": round(cells * steps / seq / 1e6, 1),
+        "speedup_vs_sequential": round(seq / wall, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "basis": "whole persistent sequence per step (HIP events), 28 B/cell-step"},
+        "grid_workgroups": grid, "band_rows_by_class": sorted(set(rows)),
+        "finite_folds": bool(np.isfinite(red["vol_total"]).all()),
+    }
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    log = lambda m: print(f"# {m}", file=sys.stderr, flush=True)
+    if args.only_batched:
+        print(json.dumps({"batched": batched_leg(args.batched_steps, args.warmup, log)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -137,6 +200,8 @@ def main():
                             "max_abs_v": float(red["max_abs_v"][-1])},
     }
     sim.close()
+    if not args.no_batched:
+        out["batched"] = batched_leg(args.batched_steps, args.warmup, log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)
