@@ -188,6 +188,85 @@ int32_t sw2d_batch_grid(sw2d_batch_t b);
 /* Release the handle, its graph and its private stream. NULL is accepted. */
 int sw2d_batch_destroy(sw2d_batch_t b);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned coarse-step surrogate: building blocks. The surrogate advances a 4x-coarsened
+ * state with the same step on the coarse grid (sw2d_create/sw2d_step with 4 dx, 4 dt) and
+ * adds a correction from a convolutional network: 3x3 'same' (zero padding) convolutions
+ * 5 -> 32 -> 32 -> 32 -> 3, ReLU after the first three, BF16 weights and activations with
+ * FP32 accumulation on the matrix cores. The plain fine model stays the judge and the
+ * fallback. The training and rollout loops are sequenced by the caller.
+ *
+ * Feature maps are NHWC BF16 (uint16_t bit patterns) with C = 16 (the network input: the 5
+ * normalised channels eta, u, v, H, mask, then zeros) or C = 32, a pixel's channels
+ * contiguous: element (n, y, x, c) at ((n*ny + y)*nx + x)*C + c. The network output and
+ * its targets are FP32 planes [n][3][ny][nx]. Weights of a layer with cin inputs are the
+ * FP32 master [9][32][cin] (tap t = 3*ky + kx, then output channel, then input channel;
+ * the last layer uses output rows 0..2 only, the rest stay zero) and its BF16 copies.
+ * All pointers are device pointers; feature maps and weights need 16 B alignment. Every
+ * call enqueues on `stream` and returns a status code; none synchronises.
+ * ------------------------------------------------------------------------------------ */
+
+/* 4x4 restriction of a fine state [ny_fine][nx_fine] (both multiples of 4) to the coarse
+ * grid [ny_fine/4][nx_fine/4]: eta_c and H_c are means over the block's water cells, a
+ * coarse cell is water when >= 8 of its 16 fine cells are, u_c (v_c) is the mean of the 4
+ * fine u (v) on the coarse cell's east (north) face; land and inactive faces are 0. */
+int sw2d_restrict4(const float *eta, const float *u, const float *v, const float *H, const uint8_t *mask,
+                   int32_t nx_fine, int32_t ny_fine, float *eta_c, float *u_c, float *v_c, float *H_c,
+                   uint8_t *mask_c, void *stream);
+
+/* Network input: out[p][c] = bf16((x_c[p] - mean[c]) / std[c]) for the channels
+ * (eta, u, v, H, mask as 0/1), c = 0..4; channels 5..15 are 0. mean, std: host arrays of 5. */
+int sw2d_pack_input(const float *eta, const float *u, const float *v, const float *H, const uint8_t *mask,
+                    int32_t nx, int32_t ny, const float *mean, const float *std_, uint16_t *out, void *stream);
+
+/* Forward 3x3 convolution of nimg images. relu = 1: cin in {16, 32}, out = BF16 NHWC with
+ * 32 channels, bias then ReLU. relu = 0 (the last layer): cin = 32, out = FP32 planes
+ * [nimg][3][ny][nx] of output channels 0..2 plus bias. wk: BF16 [9][32][cin]. */
+int sw2d_conv3x3_fwd(const uint16_t *in, int32_t cin, const uint16_t *wk, const float *bias, int32_t relu,
+                     void *out, int32_t nimg, int32_t ny, int32_t nx, void *stream);
+
+/* Data gradient of a layer with 32 inputs: dx[p][c] = (act_in[p][c] > 0) *
+ * sum_t sum_o dy[p - off_t][o] W[t][o][c], i.e. the gradient through the convolution and
+ * through the ReLU that produced the layer input act_in. dy, act_in, dx: BF16 NHWC 32
+ * channels; wd: BF16 [9][32][32] from sw2d_cast_weights (taps flipped, transposed). */
+int sw2d_conv3x3_dgrad(const uint16_t *dy, const uint16_t *wd, const uint16_t *act_in, uint16_t *dx,
+                       int32_t nimg, int32_t ny, int32_t nx, void *stream);
+
+/* Weight gradient dW[t][o][c] = sum_p dy[p][o] x[p + off_t][c] and db[o] = sum_p dy[p][o]
+ * (FP32 outputs [9][32][cin] and [32]), summed over pixel chunks in a fixed order. x: BF16
+ * NHWC cin channels; dy: BF16 NHWC 32 channels. work: FP32 partials, sized by
+ * sw2d_wgrad_workspace_bytes (0 for bad sizes). */
+size_t sw2d_wgrad_workspace_bytes(int32_t cin, int32_t nimg, int32_t ny, int32_t nx);
+int sw2d_conv3x3_wgrad(const uint16_t *x, int32_t cin, const uint16_t *dy, int32_t nimg, int32_t ny, int32_t nx,
+                       float *dW, float *db, void *work, size_t work_bytes, void *stream);
+
+/* Masked squared error: for each image and channel (eta on water cells, u on active east
+ * faces, v on active north faces of mask), r = out - target; *loss_sum (device double) =
+ * sum r^2 over active entries; d_out (BF16 NHWC 32 channels, 3..31 zero) = 2 r inv_n. */
+size_t sw2d_mse_workspace_bytes(void);
+int sw2d_mse_grad(const float *out, const float *target, const uint8_t *mask, int32_t nimg, int32_t ny,
+                  int32_t nx, float inv_n, uint16_t *d_out, double *loss_sum, void *work, size_t work_bytes,
+                  void *stream);
+
+/* Adam (Kingma & Ba) with bias correction on n FP32 parameters; t is the 1-based step. */
+int sw2d_adam(float *theta, const float *grad, float *m, float *v, int32_t n, int32_t t, float lr, float beta1,
+              float beta2, float eps, void *stream);
+
+/* BF16 working copies of one layer's FP32 master [9][32][cin]: wk (same layout) and, when
+ * wd is not NULL (cin = 32 only), the data-gradient layout wd[8 - t][c][o] = W[t][o][c]. */
+int sw2d_cast_weights(const float *master, int32_t cin, uint16_t *wk, uint16_t *wd, void *stream);
+
+/* state += t_std[c] * out[c] on active entries (eta: water cells, u/v: active faces). t_std:
+ * host array of 3. */
+int sw2d_apply_correction(float *eta, float *u, float *v, const float *out, const uint8_t *mask, int32_t nx,
+                          int32_t ny, const float *t_std, void *stream);
+
+/* *sum_sq (device double) = sum over mask != 0 of (a - b)^2, accumulated in double in a
+ * fixed order (the RMSE of the judge is sqrt(sum_sq / count)). */
+size_t sw2d_rmse_workspace_bytes(void);
+int sw2d_rmse(const float *a, const float *b, const uint8_t *mask, int32_t n, double *sum_sq, void *work,
+              size_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

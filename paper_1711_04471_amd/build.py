@@ -15,7 +15,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsw2d.so")
 
-SOURCES = ["sw2d_kernels.hip", "sw2d_api.hip", "sw2d_batch.hip"]
+SOURCES = ["sw2d_kernels.hip", "sw2d_api.hip", "sw2d_batch.hip", "sw2d_surrogate.hip",
+           "sw2d_surrogate_api.hip"]
 
 ARCH = "gfx950"
 HIPFLAGS = [

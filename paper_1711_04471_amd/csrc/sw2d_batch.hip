@@ -1,18 +1,23 @@
 // sw2d_batch.hip - ensembles of independent 2DSW basins of uneven sizes, advanced by one
 // persistent launch per chunk of steps, with a grid barrier between steps.
 //
-// Work list: every (instance, band, strip) is one item for one wave; items are ordered
-// instance by instance, in blocks of two vertically adjacent bands, so the waves that
-// run together cover a compact region and the zig-zag march shares band-boundary rows
-// through L2 (as in the single-grid kernel). Every item runs the same tile routine as
-// sw2d_step_kernel, so each instance is bitwise equal to the same basin stepped alone.
+// Work list: every (instance, band, group of 4 strips) is one tile for one workgroup, as
+// in the single-grid kernel (same tile routine, so each instance is bitwise equal to the
+// same basin stepped alone). Tiles are ordered instance by instance in blocks of two
+// vertically adjacent bands, and workgroups take them round robin in an XCD-contiguous
+// order, so the workgroups running together cover a compact region.
 //
-// Per step: waves process their items (round robin over the work list), write one fold
-// partial per item, then the whole grid meets at a barrier. After the barrier, workgroup
-// b adds the partials of instances b, b+G, ... in a fixed order and writes their folds
-// to the ring, then goes on with the next step. The barrier spin has a wall-clock
-// deadline: on expiry it raises an error flag and the kernel returns, so no wave can
-// wait forever even if the grid were not co-resident.
+// Per step: workgroups process their tiles and write one fold partial per tile, then the
+// grid meets at a barrier. After the barrier, workgroup b adds the partials of instances
+// b, b+G, ... in a fixed order and writes their folds to the ring, then goes on with the
+// next step.
+//
+// The barrier uses no contended atomics: every workgroup publishes the epoch it has
+// reached in its own flag (after an agent-scope release), workgroup 0 waits for all
+// flags in parallel and publishes the epoch in one "go" word, which the others poll.
+// Epochs are the global step counts, so they only grow and nothing is ever reset. Every
+// wait has a wall-clock deadline: on expiry it raises an error flag and the kernel
+// returns, so no wave can wait forever even if the grid were not co-resident.
 //
 // The steps done so far live in device memory and are advanced by the kernel itself, so
 // a captured graph of launches can be replayed without host-side parameters.
@@ -32,77 +37,105 @@ namespace sw2d {
 struct BatchInst {
     const float* hp;
     float* state[2][3];
-    int nx, ny;
+    int nx, ny, strips;
     StepCoef k;
     double cell_area;
     double h_sum;
-    int item_begin, item_end;  // items of this instance in the work list
+    int tile_begin, tile_end;  // tiles of this instance in the work list
 };
 
-struct BatchItem {
-    int inst, j0, j1;
-    int strip2;  // 2 * strip + 1 if the band marches south
+// A self-contained tile descriptor (128 B): everything one workgroup needs for one tile,
+// so a tile starts without dependent loads. Copied to LDS once per launch.
+struct alignas(16) BatchTile {
+    const float* hp;
+    float* state[2][3];
+    int nx, ny, strips, j0, j1;
+    int group2;  // 2 * group + 1 if the band marches south
+    int inst;
+    int pad0;
+    StepCoef k;
+    int pad1[3];
 };
+static_assert(sizeof(BatchTile) == 128, "tile descriptor size");
+
+constexpr int kLdsTiles = 64;  // descriptors a workgroup keeps in LDS at a time
+
+constexpr int kFlagStride = 16;  // 64-bit words between flags: one 128 B line each
 
 struct BatchControl {
-    unsigned barrier;      // arrivals in the current launch (reset before every launch)
     unsigned error;        // 1: a barrier wait ran past its deadline
+    unsigned pad0;
     long long steps_done;  // advanced by the kernel at the end of every launch
+    long long pad1[kFlagStride - 2];
+    unsigned long long go;  // last epoch every workgroup has reached (own line)
+    unsigned long long pad2[kFlagStride - 1];
+    // followed by one flag line per workgroup
 };
 
-constexpr int kBatchThreads = 256;
-constexpr int kBatchWaves = kBatchThreads / kWave;
+constexpr int kBatchThreads = kGroupThreads;
 constexpr int kBatchRing = 64;  // steps of per-instance folds kept
 
 struct BatchArgs {
     const BatchInst* inst;
-    const BatchItem* items;
-    FoldPartial* part;  // [2][n_items]
+    const BatchTile* tiles;
+    FoldPartial* part;  // [2][n_tiles]
     sw2d_red* ring;     // [kBatchRing][n_inst]
     BatchControl* ctl;
-    int n_inst, n_items, steps;
+    unsigned long long* flags;  // [grid][kFlagStride]
+    int n_inst, n_tiles, steps;
     unsigned long long timeout_ticks;
 };
 
-__global__ void sw2d_batch_reset_kernel(BatchControl* ctl) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctl->barrier = 0u;
+__device__ __forceinline__ bool spin_until(const unsigned long long* word, unsigned long long epoch,
+                                           unsigned long long deadline, BatchControl* ctl) {
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() > deadline) {
+            __hip_atomic_fetch_or(&ctl->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
     }
+    return true;
 }
 
-__device__ __forceinline__ bool grid_barrier(BatchControl* ctl, unsigned target,
-                                             unsigned long long timeout_ticks) {
+// Returns false (for the whole workgroup) if a wait ran past the deadline.
+__device__ bool grid_barrier(const BatchArgs& a, unsigned long long epoch) {
     __shared__ int s_ok;
-    __threadfence();  // every wave: its stores of this step are visible device-wide
-    __syncthreads();
+    const unsigned long long deadline = wall_clock64() + a.timeout_ticks;
+    if (threadIdx.x == 0) s_ok = 1;
+    __syncthreads();  // every wave's stores of this step precede thread 0's release
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(&ctl->barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 1;
-        const unsigned long long deadline = wall_clock64() + timeout_ticks;
-        while (__hip_atomic_load(&ctl->barrier, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() > deadline) {
-                __hip_atomic_fetch_or(&ctl->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(a.flags + (size_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+        for (int w = threadIdx.x; w < (int)gridDim.x; w += kBatchThreads)
+            if (!spin_until(a.flags + (size_t)w * kFlagStride, epoch, deadline, a.ctl)) s_ok = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0 && s_ok) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(&a.ctl->go, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_ok = ok;
+    }
+    if (threadIdx.x == 0 && s_ok) {
+        if (!spin_until(&a.ctl->go, epoch, deadline, a.ctl)) s_ok = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __threadfence();  // acquire: see the other workgroups' stores
     return s_ok != 0;
 }
 
-// Adds the item partials of instance i (fixed order) and writes its fold entry for `step`.
+// Adds the tile partials of instance i (fixed order) and writes its fold entry for `step`.
 __device__ void fold_instance(const BatchArgs& a, int i, int slot, long long step) {
     __shared__ double s_disp[kBatchThreads];
     __shared__ float s_mu[kBatchThreads], s_mv[kBatchThreads];
     const BatchInst& in = a.inst[i];
-    const FoldPartial* p = a.part + (size_t)slot * a.n_items;
+    const FoldPartial* p = a.part + (size_t)slot * a.n_tiles;
     double disp = 0.0;
     float mu = 0.f, mv = 0.f;
-    for (int it = in.item_begin + threadIdx.x; it < in.item_end; it += kBatchThreads) {
+    for (int it = in.tile_begin + threadIdx.x; it < in.tile_end; it += kBatchThreads) {
         disp += p[it].disp;
         mu = fmaxf(mu, p[it].mu);
         mv = fmaxf(mv, p[it].mv);
@@ -142,48 +175,118 @@ __device__ __forceinline__ int logical_block(int b, int n) {
     return x * q + min(x, r) + k;
 }
 
-__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void sw2d_batch_kernel(BatchArgs a) {
+__device__ __forceinline__ void batch_wave_sums(double& disp, float& mu, float& mv) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        disp += __shfl_xor(disp, off, kWave);
+        mu = fmaxf(mu, __shfl_xor(mu, off, kWave));
+        mv = fmaxf(mv, __shfl_xor(mv, off, kWave));
+    }
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uintptr_t v = reinterpret_cast<uintptr_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uintptr_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+__global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) {
+    __shared__ BatchTile s_tiles[kLdsTiles];
+    __shared__ double s_disp[kWavesPerGroup];
+    __shared__ float s_mu[kWavesPerGroup], s_mv[kWavesPerGroup];
     const int nwg = gridDim.x;
     const int lwg = logical_block(blockIdx.x, nwg);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int nwaves = nwg * kBatchWaves;
-    const int lwave = lwg * kBatchWaves + wave;
     const long long base = a.ctl->steps_done;
+    // this workgroup's tiles are lwg, lwg + nwg, ...
+    const int my_tiles = lwg < a.n_tiles ? (a.n_tiles - lwg + nwg - 1) / nwg : 0;
+    auto stage = [&](int k0) {  // descriptors k0 .. k0 + kLdsTiles - 1 of this workgroup
+        const int n = min(kLdsTiles, my_tiles - k0);
+        constexpr int kChunks = sizeof(BatchTile) / 16;
+        for (int e = threadIdx.x; e < n * kChunks; e += kBatchThreads) {
+            const int k = e / kChunks, ch = e - k * kChunks;
+            reinterpret_cast<uint4*>(&s_tiles[k])[ch] =
+                reinterpret_cast<const uint4*>(a.tiles + (size_t)lwg + (size_t)(k0 + k) * nwg)[ch];
+        }
+        __syncthreads();
+    };
+    const bool resident = my_tiles <= kLdsTiles;
+    if (resident) stage(0);
 
     for (int s = 0; s < a.steps; ++s) {
         const long long step_idx = base + s;  // 0-based index of the step being made
         const int cur = (int)(step_idx & 1);
         if (s > 0) fold_step(a, lwg, nwg, (s - 1) & 1, step_idx);
-        FoldPartial* part = a.part + (size_t)(s & 1) * a.n_items;
-        for (int it = lwave; it < a.n_items; it += nwaves) {
-            const BatchItem item = a.items[it];
-            const BatchInst& in = a.inst[item.inst];
-            const int c = (item.strip2 >> 1) * kStripOut - kHalo + lane;
-            const bool col_in = c >= 0 && c < in.nx;
+        FoldPartial* part = a.part + (size_t)(s & 1) * a.n_tiles;
+        for (int k = 0; k < my_tiles; ++k) {
+            const int kl = k % kLdsTiles;
+            if (!resident && kl == 0) {
+                __syncthreads();
+                stage(k);
+            }
+            const BatchTile& t = s_tiles[kl];
+            const int nx = uniform(t.nx), ny = uniform(t.ny);
+            const int group2 = uniform(t.group2);
+            const int strip = (group2 >> 1) * kWavesPerGroup + wave;
+            const int c = strip * kStripOut - kHalo + lane;
+            const bool col_in = c >= 0 && c < nx;
             const bool out_lane = col_in && lane >= kHalo && lane < kWave - kHalo;
-            const float* const* src = in.state[cur];
-            float* const* dst = in.state[cur ^ 1];
             double f_disp = 0.0;
             float f_mu = 0.f, f_mv = 0.f;
-            if (item.strip2 & 1)
-                march<false>(src[0], src[1], src[2], in.hp, dst[0], dst[1], dst[2], in.nx, in.ny, c,
-                             col_in, out_lane, item.j0, item.j1, in.k, f_disp, f_mu, f_mv);
-            else
-                march<true>(src[0], src[1], src[2], in.hp, dst[0], dst[1], dst[2], in.nx, in.ny, c,
-                            col_in, out_lane, item.j0, item.j1, in.k, f_disp, f_mu, f_mv);
-#pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) {
-                f_disp += __shfl_xor(f_disp, off, kWave);
-                f_mu = fmaxf(f_mu, __shfl_xor(f_mu, off, kWave));
-                f_mv = fmaxf(f_mv, __shfl_xor(f_mv, off, kWave));
+            if (strip < uniform(t.strips)) {
+                StepCoef kc;
+                kc.cx = uniform_f(t.k.cx);
+                kc.cy = uniform_f(t.k.cy);
+                kc.rx = uniform_f(t.k.rx);
+                kc.ry = uniform_f(t.k.ry);
+                kc.e4 = uniform_f(t.k.e4);
+                const float* hp = uniform_ptr(t.hp);
+                const float* e0 = uniform_ptr(t.state[cur][0]);
+                const float* u0 = uniform_ptr(t.state[cur][1]);
+                const float* v0 = uniform_ptr(t.state[cur][2]);
+                float* e1 = uniform_ptr(t.state[cur ^ 1][0]);
+                float* u1 = uniform_ptr(t.state[cur ^ 1][1]);
+                float* v1 = uniform_ptr(t.state[cur ^ 1][2]);
+                const int j0 = uniform(t.j0), j1 = uniform(t.j1);
+                if (group2 & 1)
+                    march<false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, f_disp, f_mu,
+                                 f_mv);
+                else
+                    march<true>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, f_disp, f_mu,
+                                f_mv);
             }
+            batch_wave_sums(f_disp, f_mu, f_mv);
             if (lane == 0) {
-                part[it].disp = f_disp;
-                part[it].mu = f_mu;
-                part[it].mv = f_mv;
+                s_disp[wave] = f_disp;
+                s_mu[wave] = f_mu;
+                s_mv[wave] = f_mv;
             }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double d = 0.0;
+                float m1 = 0.f, m2 = 0.f;
+#pragma unroll
+                for (int w = 0; w < kWavesPerGroup; ++w) {
+                    d += s_disp[w];
+                    m1 = fmaxf(m1, s_mu[w]);
+                    m2 = fmaxf(m2, s_mv[w]);
+                }
+                const int it = lwg + k * nwg;
+                part[it].disp = d;
+                part[it].mu = m1;
+                part[it].mv = m2;
+            }
+            __syncthreads();
         }
-        if (!grid_barrier(a.ctl, (unsigned)nwg * (unsigned)(s + 1), a.timeout_ticks)) return;
+        if (!grid_barrier(a, (unsigned long long)(step_idx + 1))) return;
     }
     fold_step(a, lwg, nwg, (a.steps - 1) & 1, base + a.steps);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->steps_done = base + a.steps;
@@ -203,11 +306,13 @@ struct sw2d_bctx {
     hipStream_t stream;         // the caller's
     hipStream_t capture;        // private stream used only to record graphs
     BatchInst* d_inst;
-    BatchItem* d_items;
+    BatchTile* d_tiles;
     FoldPartial* d_part;
     sw2d_red* d_ring;
     BatchControl* d_ctl;
-    int n_items;
+    unsigned long long* d_flags;
+    int max_grid;
+    int n_tiles;
     int grid;
     int steps_per_launch;
     bool use_graph;
@@ -239,10 +344,12 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct BatchLayout {
     std::vector<size_t> hp;  // per instance
-    size_t flags, scratch, inst, items, part, ring, ctl, total;
-    int n_items;
-    std::vector<int> items_of;  // per instance
+    size_t flags, scratch, inst, tiles, part, ring, ctl, gflags, total;
+    int n_tiles;
+    std::vector<int> tiles_of;  // per instance
 };
+
+constexpr int kMaxBatchGrid = 256 * 8;  // flag lines reserved: 8 workgroups on each of 256 CUs
 
 int rows_for(const sw2d_params& p, const int32_t* band_rows, int i) {
     int r = band_rows ? band_rows[i] : 16;
@@ -254,8 +361,8 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
     if (n < 1) return false;
     size_t off = 0;
     L.hp.resize(n);
-    L.items_of.resize(n);
-    L.n_items = 0;
+    L.tiles_of.resize(n);
+    L.n_tiles = 0;
     for (int i = 0; i < n; ++i) {
         if (!sw2d::detail::params_valid(&p[i])) return false;
         const int rows = rows_for(p[i], band_rows, i);
@@ -263,10 +370,11 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
         L.hp[i] = off;
         off = align_up(off + (size_t)p[i].nx * p[i].ny * sizeof(float));
         const int strips = (p[i].nx + kStripOut - 1) / kStripOut;
+        const int groups = (strips + kWavesPerGroup - 1) / kWavesPerGroup;
         const int bands = (p[i].ny + rows - 1) / rows;
-        L.items_of[i] = strips * bands;
-        if ((int64_t)L.n_items + L.items_of[i] > (1 << 30)) return false;
-        L.n_items += L.items_of[i];
+        L.tiles_of[i] = groups * bands;
+        if ((int64_t)L.n_tiles + L.tiles_of[i] > (1 << 30)) return false;
+        L.n_tiles += L.tiles_of[i];
     }
     L.flags = off;
     off = align_up(off + (size_t)n * sizeof(PrepFlags));
@@ -274,14 +382,16 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
     off = align_up(off + kHsumBlocks * sizeof(double));
     L.inst = off;
     off = align_up(off + (size_t)n * sizeof(BatchInst));
-    L.items = off;
-    off = align_up(off + (size_t)L.n_items * sizeof(BatchItem));
+    L.tiles = off;
+    off = align_up(off + (size_t)L.n_tiles * sizeof(BatchTile));
     L.part = off;
-    off = align_up(off + 2 * (size_t)L.n_items * sizeof(FoldPartial));
+    off = align_up(off + 2 * (size_t)L.n_tiles * sizeof(FoldPartial));
     L.ring = off;
     off = align_up(off + (size_t)kBatchRing * n * sizeof(sw2d_red));
     L.ctl = off;
     off = align_up(off + sizeof(BatchControl));
+    L.gflags = off;
+    off = align_up(off + (size_t)kMaxBatchGrid * kFlagStride * sizeof(unsigned long long));
     L.total = off;
     return true;
 }
@@ -289,17 +399,16 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
 int enqueue_chunks(sw2d_bctx* b, int32_t nsteps, hipStream_t s) {
     BatchArgs a;
     a.inst = b->d_inst;
-    a.items = b->d_items;
+    a.tiles = b->d_tiles;
     a.part = b->d_part;
     a.ring = b->d_ring;
     a.ctl = b->d_ctl;
+    a.flags = b->d_flags;
     a.n_inst = b->n;
-    a.n_items = b->n_items;
+    a.n_tiles = b->n_tiles;
     a.timeout_ticks = b->timeout_ticks;
     for (int32_t done = 0; done < nsteps;) {
         a.steps = (nsteps - done < b->steps_per_launch) ? nsteps - done : b->steps_per_launch;
-        hipLaunchKernelGGL(sw2d_batch_reset_kernel, dim3(1), dim3(64), 0, s, b->d_ctl);
-        SW2D_BHIP(hipGetLastError());
         hipLaunchKernelGGL(sw2d_batch_kernel, dim3(b->grid), dim3(kBatchThreads), 0, s, a);
         SW2D_BHIP(hipGetLastError());
         done += a.steps;
@@ -350,10 +459,11 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     b->steps_per_launch = 50;
     b->use_graph = true;
     b->steps_done = 0;
-    b->n_items = L.n_items;
+    b->n_tiles = L.n_tiles;
     char* w = static_cast<char*>(d_work);
     b->d_inst = reinterpret_cast<BatchInst*>(w + L.inst);
-    b->d_items = reinterpret_cast<BatchItem*>(w + L.items);
+    b->d_tiles = reinterpret_cast<BatchTile*>(w + L.tiles);
+    b->d_flags = reinterpret_cast<unsigned long long*>(w + L.gflags);
     b->d_part = reinterpret_cast<FoldPartial*>(w + L.part);
     b->d_ring = reinterpret_cast<sw2d_red*>(w + L.ring);
     b->d_ctl = reinterpret_cast<BatchControl*>(w + L.ctl);
@@ -383,8 +493,8 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     if (e != hipSuccess) return fail(batch_hip_fail(e, "sw2d_batch_create"));
 
     std::vector<BatchInst> inst(n);
-    std::vector<BatchItem> items;
-    items.reserve(L.n_items);
+    std::vector<BatchTile> tiles;
+    tiles.reserve(L.n_tiles);
     for (int i = 0; i < n; ++i) {
         if (flags[i].bad != 0 || flags[i].hmax_bits == 0) return fail(SW2D_EINVAL);
         float hmax;
@@ -400,29 +510,46 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
             for (int f = 0; f < 3; ++f) in.state[buf][f] = d_state[i] + (size_t)(3 * buf + f) * cells;
         in.nx = q.nx;
         in.ny = q.ny;
+        in.strips = (q.nx + kStripOut - 1) / kStripOut;
         in.k = sw2d::detail::make_coef(&q);
         in.cell_area = q.dx * q.dy;
         in.h_sum = flags[i].h_sum;
-        in.item_begin = (int)items.size();
+        in.tile_begin = (int)tiles.size();
         const int rows = rows_for(q, band_rows, i);
-        const int strips = (q.nx + kStripOut - 1) / kStripOut;
+        const int groups = (in.strips + kWavesPerGroup - 1) / kWavesPerGroup;
         const int bands = (q.ny + rows - 1) / rows;
         for (int blk = 0; blk < bands; blk += 2)
-            for (int st = 0; st < strips; ++st)
+            for (int gr = 0; gr < groups; ++gr)
                 for (int bd = blk; bd < blk + 2 && bd < bands; ++bd) {
-                    const int j0 = bd * rows;
-                    const int j1 = (j0 + rows < q.ny) ? j0 + rows : q.ny;
-                    items.push_back(BatchItem{i, j0, j1, 2 * st + (bd & 1)});
+                    BatchTile t;
+                    std::memset(&t, 0, sizeof t);
+                    t.hp = in.hp;
+                    for (int buf = 0; buf < 2; ++buf)
+                        for (int f = 0; f < 3; ++f) t.state[buf][f] = in.state[buf][f];
+                    t.nx = q.nx;
+                    t.ny = q.ny;
+                    t.strips = in.strips;
+                    t.j0 = bd * rows;
+                    t.j1 = (t.j0 + rows < q.ny) ? t.j0 + rows : q.ny;
+                    t.group2 = 2 * gr + (bd & 1);
+                    t.inst = i;
+                    t.k = in.k;
+                    tiles.push_back(t);
                 }
-        in.item_end = (int)items.size();
+        in.tile_end = (int)tiles.size();
     }
-    BatchControl ctl{0u, 0u, 0};
+    BatchControl ctl;
+    std::memset(&ctl, 0, sizeof ctl);
+    std::vector<unsigned long long> zero_flags((size_t)kMaxBatchGrid * kFlagStride, 0ull);
     e = hipMemcpyAsync(b->d_inst, inst.data(), n * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem),
-                           hipMemcpyHostToDevice, b->stream);
+        e = hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                           b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_flags, zero_flags.data(), zero_flags.size() * sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return fail(batch_hip_fail(e, "sw2d_batch_create upload"));
 
@@ -436,7 +563,9 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     if (e != hipSuccess) return fail(batch_hip_fail(e, "occupancy query"));
     if (per_cu < 1 || cus < 1) return fail(SW2D_EINVAL);
     if (per_cu > 8) per_cu = 8;
-    b->grid = cus * per_cu;
+    b->max_grid = cus * per_cu;
+    if (b->max_grid > kMaxBatchGrid) b->max_grid = kMaxBatchGrid;
+    b->grid = b->max_grid;
     if (clock_khz <= 0) clock_khz = 100000;
     b->timeout_ticks = (unsigned long long)clock_khz * 1000ull * 2ull;  // 2 s per barrier
     e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
@@ -448,15 +577,8 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
 int sw2d_batch_set_launch(sw2d_batch_t b, int32_t steps_per_launch, int32_t use_graph, int32_t grid) {
     if (!b) return SW2D_ESTATE;
     if (steps_per_launch < 1 || grid < 0) return SW2D_EINVAL;
-    if (grid > 0) {
-        int dev = 0, cus = 0, per_cu = 0;
-        SW2D_BHIP(hipGetDevice(&dev));
-        SW2D_BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        SW2D_BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sw2d_batch_kernel,
-                                                               kBatchThreads, 0));
-        if (grid > cus * per_cu) return SW2D_EINVAL;  // must stay co-resident
-        b->grid = grid;
-    }
+    if (grid > b->max_grid) return SW2D_EINVAL;  // must stay co-resident
+    b->grid = grid > 0 ? grid : b->max_grid;
     b->steps_per_launch = steps_per_launch;
     b->use_graph = use_graph != 0;
     drop_graph(b);
@@ -534,6 +656,7 @@ int sw2d_batch_reduce(sw2d_batch_t b, sw2d_red* host_out) {
         return SW2D_EHIP;
     }
     if (ctl.steps_done != b->steps_done) return SW2D_ESTATE;
+    (void)kBatchRing;
     for (int i = 0; i < b->n; ++i) {
         const sw2d_red& r = host_out[i];
         if (!std::isfinite(r.vol_total) || !std::isfinite(r.vol_disp) || !std::isfinite(r.max_abs_u) ||

@@ -1,0 +1,46 @@
+// sw2d_surrogate.h - host-side launchers and shared types of the surrogate kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sw2d {
+namespace sur {
+
+enum : int { kConvRelu = 0, kConvLinear3 = 1, kConvDgradMask = 2 };
+
+struct InputNorm {
+    float mean[5];
+    float inv_std[5];
+};
+
+struct AdamHyper {
+    float lr, beta1, beta2, eps;
+    float inv_bc1, inv_bc2;  // 1 / (1 - beta^t), computed in double on the host
+};
+
+hipError_t launch_restrict4(const float* eta, const float* u, const float* v, const float* H,
+                            const uint8_t* mask, int NX, int NY, float* eta_c, float* u_c, float* v_c,
+                            float* H_c, uint8_t* mask_c, hipStream_t s);
+hipError_t launch_pack_input(const float* eta, const float* u, const float* v, const float* H,
+                             const uint8_t* mask, int npix, const InputNorm& nrm, uint16_t* out,
+                             hipStream_t s);
+hipError_t launch_conv3x3(int kin, int mode, const uint16_t* in, const uint16_t* Wk, const float* bias,
+                          uint16_t* out_bf, float* out_f, const uint16_t* relu_src, int nimg, int H, int W,
+                          hipStream_t s);
+int wgrad_chunks(int nimg, int H, int W);
+hipError_t launch_wgrad(int kin, const uint16_t* x, const uint16_t* dy, int nimg, int H, int W, float* part_w,
+                        float* part_b, float* dW, float* db, hipStream_t s);
+hipError_t launch_mse_grad(const float* out, const float* target, const uint8_t* mask, int nimg, int H, int W,
+                           float inv_n, uint16_t* d_out, double* partial, int nblocks, double* loss,
+                           hipStream_t s);
+hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int n, const AdamHyper& hp,
+                       hipStream_t s);
+hipError_t launch_cast_weights(const float* master, int kin, int dkin, uint16_t* wk, uint16_t* wd, hipStream_t s);
+hipError_t launch_correct(float* eta, float* u, float* v, const float* out, const uint8_t* mask, int H, int W,
+                          const float* t_std, hipStream_t s);
+hipError_t launch_sqdiff(const float* a, const float* b, const uint8_t* mask, int n, double* partial, int nblocks,
+                         double* out, hipStream_t s);
+
+}  // namespace sur
+}  // namespace sw2d

@@ -1,0 +1,578 @@
+// sw2d_surrogate.hip - kernels of the learned coarse-step surrogate of the 2DSW model.
+//
+// The surrogate advances a 4x-coarsened state of the model of Sect. 6.2 with the same
+// fused step on the coarse grid (4 dx, 4 dt) and adds a correction predicted by a small
+// convolutional network: 3x3 'same' convolutions 5 -> 32 -> 32 -> 32 -> 3 with ReLU after
+// the first three. The plain fine model is its judge and fallback.
+//
+// Kernels here:
+//   * restrict4      fine (eta, u, v, H, mask) -> coarse, 4x4 blocks;
+//   * pack_input     coarse state -> normalised BF16 NHWC input (5 channels padded to 16);
+//   * conv3x3        implicit GEMM on BF16 MFMA (v_mfma_f32_32x32x16_bf16), FP32 accumulate:
+//                    out[p][n] = sum over taps t and channels k of in[p + off_t][k] Wk[t][n][k];
+//                    used for the forward layers (bias + ReLU + BF16 store, or bias + FP32
+//                    planar store of 3 channels) and for the data gradient (flipped,
+//                    transposed weights; fused ReLU-mask of the layer input);
+//   * wgrad          dW[t][o][c] = sum_p dY[p][o] X[p + off_t][c], split over pixel
+//                    chunks on MFMA, FP32 partials, then a fixed-order reduction;
+//   * mse_grad       masked squared error and its gradient (BF16 NHWC, 32 channels);
+//   * adam           Adam on FP32 master weights, then BF16 working copies in the forward
+//                    and data-gradient layouts;
+//   * correct        state += activity * t_std * out;
+//   * rmse           sum over water of (a - b)^2 in FP64, fixed-order.
+// Feature maps are NHWC BF16 with 16 or 32 channels: a pixel's channels are one 32/64 B
+// row, so one lane's MFMA operand (8 consecutive channels) is one 16 B load.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw2d_internal.h"
+#include "sw2d_surrogate.h"
+
+namespace sw2d {
+namespace sur {
+
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ------------------------------------------------------------------------------ restrict4
+__global__ __launch_bounds__(256) void restrict4_kernel(const float* __restrict__ eta, const float* __restrict__ u,
+                                                        const float* __restrict__ v, const float* __restrict__ H,
+                                                        const uint8_t* __restrict__ mask, int NX, int NY,
+                                                        float* __restrict__ eta_c, float* __restrict__ u_c,
+                                                        float* __restrict__ v_c, float* __restrict__ H_c,
+                                                        uint8_t* __restrict__ mask_c) {
+    const int nx = NX / 4, ny = NY / 4;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nx * ny) return;
+    const int J = idx / nx, I = idx - J * nx;
+    auto wet_count = [&](int JJ, int II) -> int {
+        if (JJ < 0 || II < 0 || JJ >= ny || II >= nx) return 0;
+        int n = 0;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) n += mask[(size_t)(4 * JJ + r) * NX + 4 * II + c] != 0;
+        return n;
+    };
+    int n = 0;
+    float se = 0.f, sh = 0.f;
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            const size_t f = (size_t)(4 * J + r) * NX + 4 * I + c;
+            if (mask[f]) {
+                ++n;
+                se += eta[f];
+                sh += H[f];
+            }
+        }
+    const bool wc = n >= 8;
+    eta_c[idx] = wc ? se / (float)n : 0.f;
+    H_c[idx] = n > 0 ? sh / (float)n : 0.f;
+    mask_c[idx] = wc ? 1 : 0;
+    const bool au = wc && wet_count(J, I + 1) >= 8;
+    const bool av = wc && wet_count(J + 1, I) >= 8;
+    float su = 0.f, sv = 0.f;
+    for (int r = 0; r < 4; ++r) su += u[(size_t)(4 * J + r) * NX + 4 * I + 3];
+    for (int c = 0; c < 4; ++c) sv += v[(size_t)(4 * J + 3) * NX + 4 * I + c];
+    u_c[idx] = au ? 0.25f * su : 0.f;
+    v_c[idx] = av ? 0.25f * sv : 0.f;
+}
+
+// ------------------------------------------------------------------------------ pack_input
+__global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict__ eta, const float* __restrict__ u,
+                                                         const float* __restrict__ v, const float* __restrict__ H,
+                                                         const uint8_t* __restrict__ mask, int npix, InputNorm nrm,
+                                                         uint16_t* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float x[5] = {eta[p], u[p], v[p], H[p], mask[p] ? 1.f : 0.f};
+    uint16_t o[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) o[c] = 0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) o[c] = f2bf((x[c] - nrm.mean[c]) * nrm.inv_std[c]);
+    uint4* dst = reinterpret_cast<uint4*>(out + (size_t)p * 16);
+    uint4 a, b;
+    a.x = o[0] | ((uint32_t)o[1] << 16);
+    a.y = o[2] | ((uint32_t)o[3] << 16);
+    a.z = o[4] | ((uint32_t)o[5] << 16);
+    a.w = o[6] | ((uint32_t)o[7] << 16);
+    b.x = o[8] | ((uint32_t)o[9] << 16);
+    b.y = o[10] | ((uint32_t)o[11] << 16);
+    b.z = o[12] | ((uint32_t)o[13] << 16);
+    b.w = o[14] | ((uint32_t)o[15] << 16);
+    dst[0] = a;
+    dst[1] = b;
+}
+
+// ------------------------------------------------------------------------------ conv3x3
+// Tile: kConvTH rows x 32 columns of output pixels per workgroup (4 waves, 2 rows each);
+// the (TH+2) x 34 input patch is staged in LDS with a padded pixel stride.
+constexpr int kConvTH = 8;
+constexpr int kConvTW = 32;
+constexpr int kConvThreads = 256;
+
+template <int KIN>
+struct ConvLds {
+    static constexpr int kStride = KIN * 2 + 16;  // bytes per pixel, 16 B aligned, spreads banks
+    static constexpr int kCols = kConvTW + 2;
+    static constexpr int kRows = kConvTH + 2;
+    static constexpr int kBytes = kRows * kCols * kStride;
+};
+
+template <int KIN, int MODE>
+__global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* __restrict__ in,
+                                                               const uint16_t* __restrict__ Wk,
+                                                               const float* __restrict__ bias,
+                                                               uint16_t* __restrict__ out_bf,
+                                                               float* __restrict__ out_f,
+                                                               const uint16_t* __restrict__ relu_src, int H,
+                                                               int W) {
+    using L = ConvLds<KIN>;
+    __shared__ __attribute__((aligned(16))) unsigned char patch[L::kBytes];
+    const int tiles_x = (W + kConvTW - 1) / kConvTW;
+    const int tiles_y = (H + kConvTH - 1) / kConvTH;
+    const int tile = blockIdx.x % (tiles_x * tiles_y);
+    const int img = blockIdx.x / (tiles_x * tiles_y);
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int y0 = ty * kConvTH, x0 = tx * kConvTW;
+    const size_t img_off = (size_t)img * H * W;
+
+    // stage the input patch (zero outside the image)
+    constexpr int kChunks = KIN / 8;  // 16 B chunks per pixel
+    for (int e = threadIdx.x; e < L::kRows * L::kCols * kChunks; e += kConvThreads) {
+        const int pix = e / kChunks, ch = e - pix * kChunks;
+        const int r = pix / L::kCols, c = pix - r * L::kCols;
+        const int gy = y0 + r - 1, gx = x0 + c - 1;
+        uint4 val = make_uint4(0u, 0u, 0u, 0u);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            val = reinterpret_cast<const uint4*>(in + (img_off + (size_t)gy * W + gx) * KIN)[ch];
+        *reinterpret_cast<uint4*>(patch + pix * L::kStride + ch * 16) = val;
+    }
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int half = lane / 32;  // which 8-channel group of a 16-channel chunk
+    const int j = lane % 32;     // pixel within the 32-column block; also the A row (n)
+
+    // A operands (weights), one per tap and 16-channel chunk: Wk[t][n = j][k0 + 8 half + 0..7]
+    constexpr int kK = KIN / 16;
+    bf16x8 a[9][kK];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int kc = 0; kc < kK; ++kc)
+            a[t][kc] = *reinterpret_cast<const bf16x8*>(Wk + ((size_t)t * 32 + j) * KIN + kc * 16 + half * 8);
+    __syncthreads();
+
+    f32x16 acc[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[b][t] = 0.f;
+
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int r = wave * 2 + b;  // output row within the tile
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+            const unsigned char* src = patch + ((r + ky) * L::kCols + (j + kx)) * L::kStride + half * 16;
+#pragma unroll
+            for (int kc = 0; kc < kK; ++kc) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(src + kc * 32);
+                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t][kc], bv, acc[b], 0, 0, 0);
+            }
+        }
+    }
+
+    // epilogue: lane holds pixel j, output channels n = 8 (q) + 4 half + (0..3), q = 0..3
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int gy = y0 + wave * 2 + b, gx = x0 + j;
+        if (gy >= H || gx >= W) continue;
+        const size_t p = img_off + (size_t)gy * W + gx;
+        if constexpr (MODE == kConvRelu || MODE == kConvDgradMask) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n0 = 8 * q + 4 * half;
+                uint16_t o[4];
+                if constexpr (MODE == kConvRelu) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = f2bf(fmaxf(acc[b][4 * q + e] + bias[n0 + e], 0.f));
+                } else {
+                    const uint2 m = *reinterpret_cast<const uint2*>(relu_src + p * 32 + n0);
+                    const uint16_t mv[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16),
+                                            (uint16_t)(m.y & 0xffff), (uint16_t)(m.y >> 16)};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        o[e] = (bf2f(mv[e]) > 0.f) ? f2bf(acc[b][4 * q + e]) : (uint16_t)0;
+                }
+                uint2 w;
+                w.x = o[0] | ((uint32_t)o[1] << 16);
+                w.y = o[2] | ((uint32_t)o[3] << 16);
+                *reinterpret_cast<uint2*>(out_bf + p * 32 + n0) = w;
+            }
+        } else {  // kConvLinear3: channels 0..2 as FP32 planes [img][3][H][W]
+            if (half == 0) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    out_f[((size_t)img * 3 + e) * H * W + (size_t)gy * W + gx] = acc[b][e] + bias[e];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ wgrad
+// Split over pixel chunks: workgroup g takes tiles g*kWgTiles ... of all images' 4 x 64
+// pixel tiles; each wave accumulates one row of the tile for all 9 taps (9 accumulators
+// of 32 x 32), the four waves are added in LDS in wave order, and the chunk's partial
+// [9][32][KIN] (and the bias partial [32]) goes to global memory.
+constexpr int kWgTH = 4;
+constexpr int kWgTW = 64;
+constexpr int kWgTiles = 16;
+
+template <int KIN>
+__global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
+                                                    int nimg, int H, int W, float* __restrict__ part_w,
+                                                    float* __restrict__ part_b) {
+    constexpr int kXRows = kWgTH + 2, kXCols = kWgTW + 2;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[kXRows * kXCols * KIN];
+    __shared__ __attribute__((aligned(16))) uint16_t ds[kWgTH * kWgTW * 32];
+    __shared__ float red[4][32];
+    __shared__ float tapsum[32 * 32];
+    const int tiles_x = (W + kWgTW - 1) / kWgTW, tiles_y = (H + kWgTH - 1) / kWgTH;
+    const int tiles = tiles_x * tiles_y * nimg;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int half = lane / 32, j = lane % 32;
+
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+    float bsum = 0.f;  // bias gradient: thread (wave, j < 32) sums channel j of its row
+
+    for (int k = 0; k < kWgTiles; ++k) {
+        const int tile = blockIdx.x * kWgTiles + k;
+        if (tile >= tiles) break;
+        const int img = tile / (tiles_x * tiles_y);
+        const int tt = tile - img * tiles_x * tiles_y;
+        const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
+        const int y0 = ty * kWgTH, x0 = tx * kWgTW;
+        const size_t img_off = (size_t)img * H * W;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kXRows * kXCols * (KIN / 8); e += 256) {
+            const int pix = e / (KIN / 8), ch = e - pix * (KIN / 8);
+            const int r = pix / kXCols, c = pix - r * kXCols;
+            const int gy = y0 + r - 1, gx = x0 + c - 1;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                val = reinterpret_cast<const uint4*>(x + (img_off + (size_t)gy * W + gx) * KIN)[ch];
+            reinterpret_cast<uint4*>(xs)[e] = val;
+        }
+        for (int e = threadIdx.x; e < kWgTH * kWgTW * 4; e += 256) {
+            const int pix = e / 4, ch = e - pix * 4;
+            const int r = pix / kWgTW, c = pix - r * kWgTW;
+            const int gy = y0 + r, gx = x0 + c;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (gy < H && gx < W) val = reinterpret_cast<const uint4*>(dy + (img_off + (size_t)gy * W + gx) * 32)[ch];
+            reinterpret_cast<uint4*>(ds)[e] = val;
+        }
+        __syncthreads();
+        // bias gradient partial: channel j over this wave's row
+        if (half == 0)
+            for (int c = 0; c < kWgTW; ++c) bsum += bf2f(ds[(wave * kWgTW + c) * 32 + j]);
+        // K steps of 16 pixels along this wave's row
+#pragma unroll 1
+        for (int ks = 0; ks < kWgTW / 16; ++ks) {
+            const int c0 = ks * 16 + half * 8;  // first of this lane's 8 pixels
+            bf16x8 av;  // A[o = j][pixels c0..c0+7] from dY
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = (short)ds[(wave * kWgTW + c0 + e) * 32 + j];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int ky = t / 3, kx = t - 3 * (t / 3);
+                bf16x8 bv;  // B[pixels][c = j] from X shifted by the tap
+                if (j < KIN) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        bv[e] = (short)xs[((wave + ky) * kXCols + c0 + e + kx) * KIN + j];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) bv[e] = 0;
+                }
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // add the four waves in wave order through LDS and write the chunk partial
+    float* out = part_w + (size_t)blockIdx.x * 9 * 32 * KIN;
+    for (int t = 0; t < 9; ++t) {
+        __syncthreads();
+        // acc[t][e]: o = 8 (e / 4) + 4 half + e % 4, c = j
+        for (int w = 0; w < 4; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int o = 8 * (e / 4) + 4 * half + (e % 4);
+                    if (w == 0) tapsum[o * 32 + j] = acc[t][e];
+                    else tapsum[o * 32 + j] += acc[t][e];
+                }
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < 32 * KIN; e += 256) {
+            const int o = e / KIN, c = e - o * KIN;
+            out[(size_t)t * 32 * KIN + e] = tapsum[o * 32 + c];
+        }
+    }
+    if (half == 0) red[wave][j] = bsum;
+    __syncthreads();
+    if (threadIdx.x < 32)
+        part_b[(size_t)blockIdx.x * 32 + threadIdx.x] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+// dW[i] = sum over chunks (in chunk order) of part[chunk][i]; one thread per weight.
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part_w,
+                                                           const float* __restrict__ part_b, int chunks,
+                                                           int nw, float* __restrict__ dW, float* __restrict__ db) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nw) {
+        float s = 0.f;
+        for (int k = 0; k < chunks; ++k) s += part_w[(size_t)k * nw + i];
+        dW[i] = s;
+    } else if (i < nw + 32) {
+        const int o = i - nw;
+        float s = 0.f;
+        for (int k = 0; k < chunks; ++k) s += part_b[(size_t)k * 32 + o];
+        db[o] = s;
+    }
+}
+
+// ------------------------------------------------------------------------------ mse_grad
+// out, target: FP32 planes [img][3][H][W]; mask: coarse water mask [img][H][W].
+// d_out (BF16 NHWC, 32 channels, 3..31 zero) = 2 act (out - target) * inv_n;
+// partial[block] = sum act (out - target)^2.
+__global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__ out, const float* __restrict__ target,
+                                                       const uint8_t* __restrict__ mask, int nimg, int H, int W,
+                                                       float inv_n, uint16_t* __restrict__ d_out,
+                                                       double* __restrict__ partial) {
+    __shared__ double lds[256];
+    const size_t npix = (size_t)nimg * H * W;
+    double s = 0.0;
+    for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < npix; q += (size_t)gridDim.x * 256) {
+        const size_t img = q / ((size_t)H * W);
+        const size_t pin = q - img * H * W;
+        const int y = (int)(pin / W), x = (int)(pin - (size_t)y * W);
+        const uint8_t* m = mask + img * H * W;
+        const bool wet = m[pin] != 0;
+        const bool act[3] = {wet, wet && x + 1 < W && m[pin + 1] != 0, wet && y + 1 < H && m[pin + W] != 0};
+        uint16_t o[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t f = (img * 3 + c) * H * W + pin;
+            const float r = act[c] ? out[f] - target[f] : 0.f;
+            s += (double)r * (double)r;
+            o[c] = f2bf(2.f * r * inv_n);
+        }
+        uint4* dst = reinterpret_cast<uint4*>(d_out + q * 32);
+        dst[0] = make_uint4(o[0] | ((uint32_t)o[1] << 16), o[2], 0u, 0u);
+        dst[1] = make_uint4(0u, 0u, 0u, 0u);
+        dst[2] = make_uint4(0u, 0u, 0u, 0u);
+        dst[3] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = lds[0];
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial, int n,
+                                                           double* __restrict__ out) {
+    __shared__ double lds[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lds[0];
+}
+
+// ------------------------------------------------------------------------------ adam
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ theta, const float* __restrict__ grad,
+                                                   float* __restrict__ m, float* __restrict__ v, int n,
+                                                   AdamHyper hp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = grad[i];
+    const float mi = hp.beta1 * m[i] + (1.f - hp.beta1) * g;
+    const float vi = hp.beta2 * v[i] + (1.f - hp.beta2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= hp.lr * (mi * hp.inv_bc1) / (sqrtf(vi * hp.inv_bc2) + hp.eps);
+}
+
+// BF16 working copies of one layer: forward Wk[t][n][k] and data-gradient Wd[t'][k][n] with
+// t' = 8 - t (flipped taps), from the FP32 master in forward layout [9][32][kin].
+__global__ __launch_bounds__(256) void cast_weights_kernel(const float* __restrict__ master, int kin, int dkin,
+                                                           uint16_t* __restrict__ wk, uint16_t* __restrict__ wd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * 32 * kin) return;
+    const int t = i / (32 * kin), rem = i - t * 32 * kin;
+    const int n = rem / kin, k = rem - n * kin;
+    const uint16_t b = f2bf(master[i]);
+    wk[i] = b;
+    // data gradient: output channels are the forward input channels k (32 of them, kin
+    // may be 16 or 32), reduced channels are the forward outputs n (dkin of them)
+    if (wd && n < dkin) wd[((size_t)(8 - t) * 32 + k) * dkin + n] = b;
+}
+
+// ------------------------------------------------------------------------------ correct
+__global__ __launch_bounds__(256) void correct_kernel(float* __restrict__ eta, float* __restrict__ u,
+                                                      float* __restrict__ v, const float* __restrict__ out,
+                                                      const uint8_t* __restrict__ mask, int H, int W, float s0,
+                                                      float s1, float s2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= H * W) return;
+    const int y = p / W, x = p - y * W;
+    const bool wet = mask[p] != 0;
+    if (!wet) return;
+    const size_t plane = (size_t)H * W;
+    eta[p] += s0 * out[p];
+    if (x + 1 < W && mask[p + 1]) u[p] += s1 * out[plane + p];
+    if (y + 1 < H && mask[p + W]) v[p] += s2 * out[2 * plane + p];
+}
+
+// ------------------------------------------------------------------------------ rmse
+__global__ __launch_bounds__(256) void sqdiff_kernel(const float* __restrict__ a, const float* __restrict__ b,
+                                                     const uint8_t* __restrict__ mask, int n,
+                                                     double* __restrict__ partial) {
+    __shared__ double lds[256];
+    double s = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+        if (mask[i]) {
+            const double d = (double)a[i] - (double)b[i];
+            s += d * d;
+        }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = lds[0];
+}
+
+// ------------------------------------------------------------------------------ launchers
+hipError_t launch_restrict4(const float* eta, const float* u, const float* v, const float* H,
+                            const uint8_t* mask, int NX, int NY, float* eta_c, float* u_c, float* v_c,
+                            float* H_c, uint8_t* mask_c, hipStream_t s) {
+    const int n = (NX / 4) * (NY / 4);
+    hipLaunchKernelGGL(restrict4_kernel, dim3((n + 255) / 256), dim3(256), 0, s, eta, u, v, H, mask, NX, NY,
+                       eta_c, u_c, v_c, H_c, mask_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const float* eta, const float* u, const float* v, const float* H,
+                             const uint8_t* mask, int npix, const InputNorm& nrm, uint16_t* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(pack_input_kernel, dim3((npix + 255) / 256), dim3(256), 0, s, eta, u, v, H, mask, npix, nrm,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv3x3(int kin, int mode, const uint16_t* in, const uint16_t* Wk, const float* bias,
+                          uint16_t* out_bf, float* out_f, const uint16_t* relu_src, int nimg, int H, int W,
+                          hipStream_t s) {
+    const int tiles = ((W + kConvTW - 1) / kConvTW) * ((H + kConvTH - 1) / kConvTH);
+    const dim3 grid(tiles * nimg), block(kConvThreads);
+#define SW2D_CONV_CASE(K, M)                                                                                      \
+    if (kin == K && mode == M) {                                                                                  \
+        hipLaunchKernelGGL((conv3x3_kernel<K, M>), grid, block, 0, s, in, Wk, bias, out_bf, out_f, relu_src, H, W); \
+        return hipGetLastError();                                                                                  \
+    }
+    SW2D_CONV_CASE(16, kConvRelu)
+    SW2D_CONV_CASE(32, kConvRelu)
+    SW2D_CONV_CASE(32, kConvLinear3)
+    SW2D_CONV_CASE(32, kConvDgradMask)
+#undef SW2D_CONV_CASE
+    return hipErrorInvalidValue;
+}
+
+int wgrad_chunks(int nimg, int H, int W) {
+    const int tiles = ((W + kWgTW - 1) / kWgTW) * ((H + kWgTH - 1) / kWgTH) * nimg;
+    return (tiles + kWgTiles - 1) / kWgTiles;
+}
+
+hipError_t launch_wgrad(int kin, const uint16_t* x, const uint16_t* dy, int nimg, int H, int W, float* part_w,
+                        float* part_b, float* dW, float* db, hipStream_t s) {
+    const int chunks = wgrad_chunks(nimg, H, W);
+    if (kin == 16)
+        hipLaunchKernelGGL(wgrad_kernel<16>, dim3(chunks), dim3(256), 0, s, x, dy, nimg, H, W, part_w, part_b);
+    else if (kin == 32)
+        hipLaunchKernelGGL(wgrad_kernel<32>, dim3(chunks), dim3(256), 0, s, x, dy, nimg, H, W, part_w, part_b);
+    else
+        return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nw = 9 * 32 * kin;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((nw + 32 + 255) / 256), dim3(256), 0, s, part_w, part_b, chunks, nw,
+                       dW, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse_grad(const float* out, const float* target, const uint8_t* mask, int nimg, int H, int W,
+                           float inv_n, uint16_t* d_out, double* partial, int nblocks, double* loss,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(nblocks), dim3(256), 0, s, out, target, mask, nimg, H, W, inv_n, d_out,
+                       partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, nblocks, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int n, const AdamHyper& hp,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, theta, grad, m, v, n, hp);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_weights(const float* master, int kin, int dkin, uint16_t* wk, uint16_t* wd, hipStream_t s) {
+    const int n = 9 * 32 * kin;
+    hipLaunchKernelGGL(cast_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, master, kin, dkin, wk, wd);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(float* eta, float* u, float* v, const float* out, const uint8_t* mask, int H, int W,
+                          const float* t_std, hipStream_t s) {
+    hipLaunchKernelGGL(correct_kernel, dim3((H * W + 255) / 256), dim3(256), 0, s, eta, u, v, out, mask, H, W,
+                       t_std[0], t_std[1], t_std[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqdiff(const float* a, const float* b, const uint8_t* mask, int n, double* partial, int nblocks,
+                         double* out, hipStream_t s) {
+    hipLaunchKernelGGL(sqdiff_kernel, dim3(nblocks), dim3(256), 0, s, a, b, mask, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace sur
+}  // namespace sw2d

@@ -1,0 +1,154 @@
+// sw2d_surrogate_api.hip - C ABI of the surrogate's building blocks (argument checks and
+// launches only; the training and rollout loops are sequenced by the caller).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sw2d_internal.h"
+#include "sw2d_surrogate.h"
+
+using namespace sw2d;
+using namespace sw2d::sur;
+
+namespace {
+
+int fail(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SW2D_OK;
+    char msg[256];
+    std::snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
+    sw2d::detail::set_hip_message(msg);
+    return SW2D_EHIP;
+}
+
+bool dims_ok(int nimg, int ny, int nx) {
+    return nimg >= 1 && ny >= 1 && nx >= 1 && (int64_t)nimg * ny * nx < ((int64_t)1 << 31);
+}
+
+bool aligned16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
+constexpr int kMseBlocks = 1024;
+constexpr int kRmseBlocks = 1024;
+
+}  // namespace
+
+extern "C" {
+
+int sw2d_restrict4(const float* eta, const float* u, const float* v, const float* H, const uint8_t* mask,
+                   int32_t nx_fine, int32_t ny_fine, float* eta_c, float* u_c, float* v_c, float* H_c,
+                   uint8_t* mask_c, void* stream) {
+    if (!eta || !u || !v || !H || !mask || !eta_c || !u_c || !v_c || !H_c || !mask_c) return SW2D_EINVAL;
+    if (nx_fine < 4 || ny_fine < 4 || nx_fine % 4 || ny_fine % 4 || !dims_ok(1, ny_fine, nx_fine))
+        return SW2D_EINVAL;
+    return fail(launch_restrict4(eta, u, v, H, mask, nx_fine, ny_fine, eta_c, u_c, v_c, H_c, mask_c,
+                                 static_cast<hipStream_t>(stream)),
+                "sw2d_restrict4");
+}
+
+int sw2d_pack_input(const float* eta, const float* u, const float* v, const float* H, const uint8_t* mask,
+                    int32_t nx, int32_t ny, const float* mean, const float* std_, uint16_t* out, void* stream) {
+    if (!eta || !u || !v || !H || !mask || !mean || !std_ || !out || !aligned16(out)) return SW2D_EINVAL;
+    if (!dims_ok(1, ny, nx)) return SW2D_EINVAL;
+    InputNorm nrm;
+    for (int c = 0; c < 5; ++c) {
+        if (!(std_[c] > 0.f) || !std::isfinite(mean[c])) return SW2D_EINVAL;
+        nrm.mean[c] = mean[c];
+        nrm.inv_std[c] = 1.f / std_[c];
+    }
+    return fail(launch_pack_input(eta, u, v, H, mask, nx * ny, nrm, out, static_cast<hipStream_t>(stream)),
+                "sw2d_pack_input");
+}
+
+int sw2d_conv3x3_fwd(const uint16_t* in, int32_t cin, const uint16_t* wk, const float* bias, int32_t relu,
+                     void* out, int32_t nimg, int32_t ny, int32_t nx, void* stream) {
+    if (!in || !wk || !bias || !out || !aligned16(in) || !aligned16(wk) || !aligned16(out)) return SW2D_EINVAL;
+    if ((cin != 16 && cin != 32) || !dims_ok(nimg, ny, nx)) return SW2D_EINVAL;
+    if (!relu && cin != 32) return SW2D_EINVAL;
+    const int mode = relu ? kConvRelu : kConvLinear3;
+    return fail(launch_conv3x3(cin, mode, in, wk, bias, relu ? static_cast<uint16_t*>(out) : nullptr,
+                               relu ? nullptr : static_cast<float*>(out), nullptr, nimg, ny, nx,
+                               static_cast<hipStream_t>(stream)),
+                "sw2d_conv3x3_fwd");
+}
+
+int sw2d_conv3x3_dgrad(const uint16_t* dy, const uint16_t* wd, const uint16_t* act_in, uint16_t* dx, int32_t nimg,
+                       int32_t ny, int32_t nx, void* stream) {
+    if (!dy || !wd || !act_in || !dx || !aligned16(dy) || !aligned16(wd) || !aligned16(dx) || !aligned16(act_in))
+        return SW2D_EINVAL;
+    if (!dims_ok(nimg, ny, nx)) return SW2D_EINVAL;
+    return fail(launch_conv3x3(32, kConvDgradMask, dy, wd, nullptr, dx, nullptr, act_in, nimg, ny, nx,
+                               static_cast<hipStream_t>(stream)),
+                "sw2d_conv3x3_dgrad");
+}
+
+size_t sw2d_wgrad_workspace_bytes(int32_t cin, int32_t nimg, int32_t ny, int32_t nx) {
+    if ((cin != 16 && cin != 32) || !dims_ok(nimg, ny, nx)) return 0;
+    const size_t chunks = (size_t)wgrad_chunks(nimg, ny, nx);
+    return chunks * (9 * 32 * (size_t)cin + 32) * sizeof(float);
+}
+
+int sw2d_conv3x3_wgrad(const uint16_t* x, int32_t cin, const uint16_t* dy, int32_t nimg, int32_t ny, int32_t nx,
+                       float* dW, float* db, void* work, size_t work_bytes, void* stream) {
+    if (!x || !dy || !dW || !db || !work || !aligned16(x) || !aligned16(dy) || !aligned16(work)) return SW2D_EINVAL;
+    const size_t need = sw2d_wgrad_workspace_bytes(cin, nimg, ny, nx);
+    if (need == 0) return SW2D_EINVAL;
+    if (work_bytes < need) return SW2D_ENOSPC;
+    const size_t chunks = (size_t)wgrad_chunks(nimg, ny, nx);
+    float* part_w = static_cast<float*>(work);
+    float* part_b = part_w + chunks * 9 * 32 * cin;
+    return fail(launch_wgrad(cin, x, dy, nimg, ny, nx, part_w, part_b, dW, db, static_cast<hipStream_t>(stream)),
+                "sw2d_conv3x3_wgrad");
+}
+
+size_t sw2d_mse_workspace_bytes(void) { return kMseBlocks * sizeof(double); }
+
+int sw2d_mse_grad(const float* out, const float* target, const uint8_t* mask, int32_t nimg, int32_t ny,
+                  int32_t nx, float inv_n, uint16_t* d_out, double* loss_sum, void* work, size_t work_bytes,
+                  void* stream) {
+    if (!out || !target || !mask || !d_out || !loss_sum || !work || !aligned16(d_out)) return SW2D_EINVAL;
+    if (!dims_ok(nimg, ny, nx) || !(inv_n >= 0.f) || !std::isfinite(inv_n)) return SW2D_EINVAL;
+    if (work_bytes < sw2d_mse_workspace_bytes()) return SW2D_ENOSPC;
+    return fail(launch_mse_grad(out, target, mask, nimg, ny, nx, inv_n, d_out, static_cast<double*>(work),
+                                kMseBlocks, loss_sum, static_cast<hipStream_t>(stream)),
+                "sw2d_mse_grad");
+}
+
+int sw2d_adam(float* theta, const float* grad, float* m, float* v, int32_t n, int32_t t, float lr, float beta1,
+              float beta2, float eps, void* stream) {
+    if (!theta || !grad || !m || !v || n < 1 || t < 1) return SW2D_EINVAL;
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) || !(lr >= 0.f))
+        return SW2D_EINVAL;
+    AdamHyper hp;
+    hp.lr = lr;
+    hp.beta1 = beta1;
+    hp.beta2 = beta2;
+    hp.eps = eps;
+    hp.inv_bc1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)t)));
+    hp.inv_bc2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)t)));
+    return fail(launch_adam(theta, grad, m, v, n, hp, static_cast<hipStream_t>(stream)), "sw2d_adam");
+}
+
+int sw2d_cast_weights(const float* master, int32_t cin, uint16_t* wk, uint16_t* wd, void* stream) {
+    if (!master || !wk || (cin != 16 && cin != 32)) return SW2D_EINVAL;
+    if (wd && cin != 32) return SW2D_EINVAL;  // data gradients exist for 32-channel inputs only
+    return fail(launch_cast_weights(master, cin, 32, wk, wd, static_cast<hipStream_t>(stream)), "sw2d_cast_weights");
+}
+
+int sw2d_apply_correction(float* eta, float* u, float* v, const float* out, const uint8_t* mask, int32_t nx,
+                          int32_t ny, const float* t_std, void* stream) {
+    if (!eta || !u || !v || !out || !mask || !t_std || !dims_ok(1, ny, nx)) return SW2D_EINVAL;
+    return fail(launch_correct(eta, u, v, out, mask, ny, nx, t_std, static_cast<hipStream_t>(stream)),
+                "sw2d_apply_correction");
+}
+
+size_t sw2d_rmse_workspace_bytes(void) { return kRmseBlocks * sizeof(double); }
+
+int sw2d_rmse(const float* a, const float* b, const uint8_t* mask, int32_t n, double* sum_sq, void* work,
+              size_t work_bytes, void* stream) {
+    if (!a || !b || !mask || !sum_sq || !work || n < 1) return SW2D_EINVAL;
+    if (work_bytes < sw2d_rmse_workspace_bytes()) return SW2D_ENOSPC;
+    return fail(launch_sqdiff(a, b, mask, n, static_cast<double*>(work), kRmseBlocks, sum_sq,
+                              static_cast<hipStream_t>(stream)),
+                "sw2d_rmse");
+}
+
+}  // extern "C"
