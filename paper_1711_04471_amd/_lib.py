@@ -33,6 +33,7 @@ assert ctypes.sizeof(sw2d_red) == 32
 
 _vp = ctypes.c_void_p
 _pp = ctypes.POINTER(ctypes.c_void_p)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 # name -> (restype, argtypes); every symbol the public header declares
 SIGNATURES = {
@@ -64,6 +65,23 @@ SIGNATURES = {
     "sw2d_batch_set_barrier_timeout": (ctypes.c_int, [_vp, ctypes.c_double]),
     "sw2d_batch_grid": (ctypes.c_int32, [_vp]),
     "sw2d_batch_destroy": (ctypes.c_int, [_vp]),
+    # surrogate building blocks
+    "sw2d_restrict4": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 + [_vp] * 6),
+    "sw2d_pack_input": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 + [_fp, _fp, _vp, _vp]),
+    "sw2d_conv3x3_fwd": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp] +
+                         [ctypes.c_int32] * 3 + [_vp]),
+    "sw2d_conv3x3_dgrad": (ctypes.c_int, [_vp] * 4 + [ctypes.c_int32] * 3 + [_vp]),
+    "sw2d_wgrad_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32] * 4),
+    "sw2d_conv3x3_wgrad": (ctypes.c_int, [_vp, ctypes.c_int32, _vp] + [ctypes.c_int32] * 3 +
+                           [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "sw2d_mse_workspace_bytes": (ctypes.c_size_t, []),
+    "sw2d_mse_grad": (ctypes.c_int, [_vp] * 3 + [ctypes.c_int32] * 3 +
+                      [ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "sw2d_adam": (ctypes.c_int, [_vp] * 4 + [ctypes.c_int32] * 2 + [ctypes.c_float] * 4 + [_vp]),
+    "sw2d_cast_weights": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "sw2d_apply_correction": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 + [_fp, _vp]),
+    "sw2d_rmse_workspace_bytes": (ctypes.c_size_t, []),
+    "sw2d_rmse": (ctypes.c_int, [_vp] * 3 + [ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]),
     "sw2d_last_hip_error": (ctypes.c_char_p, []),
 }
 
