@@ -214,10 +214,14 @@ int sw2d_restrict4(const float *eta, const float *u, const float *v, const float
                    int32_t nx_fine, int32_t ny_fine, float *eta_c, float *u_c, float *v_c, float *H_c,
                    uint8_t *mask_c, void *stream);
 
-/* Network input: out[p][c] = bf16((x_c[p] - mean[c]) / std[c]) for the channels
- * (eta, u, v, H, mask as 0/1), c = 0..4; channels 5..15 are 0. mean, std: host arrays of 5. */
+/* Network input: out[p][c] = bf16((x_c[p] - mean[c]) / std[c] + noise) for the channels
+ * (eta, u, v, H, mask as 0/1), c = 0..4; channels 5..15 are 0. mean, std: host arrays of 5.
+ * noise (training only; 0 when noise_amp = 0) is added to channels 0..2: noise_amp * U,
+ * U uniform in [-1, 1) from SplitMix64 (Steele, Lea & Flood 2014): z = noise_seed +
+ * (3 p + c + 1) * 0x9E3779B97F4A7C15, the SplitMix64 finaliser, U = (z >> 40) / 2^23 - 1. */
 int sw2d_pack_input(const float *eta, const float *u, const float *v, const float *H, const uint8_t *mask,
-                    int32_t nx, int32_t ny, const float *mean, const float *std_, uint16_t *out, void *stream);
+                    int32_t nx, int32_t ny, const float *mean, const float *std_, float noise_amp,
+                    uint64_t noise_seed, uint16_t *out, void *stream);
 
 /* Forward 3x3 convolution of nimg images. relu = 1: cin in {16, 32}, out = BF16 NHWC with
  * 32 channels, bias then ReLU. relu = 0 (the last layer): cin = 32, out = FP32 planes
@@ -241,12 +245,23 @@ int sw2d_conv3x3_wgrad(const uint16_t *x, int32_t cin, const uint16_t *dy, int32
                        float *dW, float *db, void *work, size_t work_bytes, void *stream);
 
 /* Masked squared error: for each image and channel (eta on water cells, u on active east
- * faces, v on active north faces of mask), r = out - target; *loss_sum (device double) =
- * sum r^2 over active entries; d_out (BF16 NHWC 32 channels, 3..31 zero) = 2 r inv_n. */
+ * faces, v on active north faces of mask), r = out - target_scale[c] * target; *loss_sum
+ * (device double) = sum r^2 over active entries; d_out (BF16 NHWC 32 channels, 3..31
+ * zero) = 2 r inv_n. target_scale: host array of 3. */
 size_t sw2d_mse_workspace_bytes(void);
-int sw2d_mse_grad(const float *out, const float *target, const uint8_t *mask, int32_t nimg, int32_t ny,
-                  int32_t nx, float inv_n, uint16_t *d_out, double *loss_sum, void *work, size_t work_bytes,
-                  void *stream);
+int sw2d_mse_grad(const float *out, const float *target, const float *target_scale, const uint8_t *mask,
+                  int32_t nimg, int32_t ny, int32_t nx, float inv_n, uint16_t *d_out, double *loss_sum, void *work,
+                  size_t work_bytes, void *stream);
+
+/* Training targets: out[c][p] = a_c[p] - b_c[p] for c = 0, 1, 2 (out: FP32 [3][n]). */
+int sw2d_sub3(const float *a0, const float *a1, const float *a2, const float *b0, const float *b1,
+              const float *b2, int32_t n, float *out, void *stream);
+
+/* out2[0] = sum x, out2[1] = sum x^2 (device doubles, fixed order) over the n entries with
+ * mask != 0 (all entries if mask is NULL): the normalisation statistics. */
+size_t sw2d_moments_workspace_bytes(void);
+int sw2d_moments(const float *x, const uint8_t *mask, int64_t n, double *out2, void *work, size_t work_bytes,
+                 void *stream);
 
 /* Adam (Kingma & Ba) with bias correction on n FP32 parameters; t is the 1-based step. */
 int sw2d_adam(float *theta, const float *grad, float *m, float *v, int32_t n, int32_t t, float lr, float beta1,

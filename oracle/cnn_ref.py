@@ -164,10 +164,36 @@ def adam_step(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 # --------------------------------------------------------------------------- surrogate glue
-def normalise(eta, u, v, H, mask, mean, std):
-    """The 5 input channels (eta, u, v, H, mask), each shifted and scaled: (x - mean) / std."""
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed, i):
+    """SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) output for counter i: the state
+    seed + (i + 1) * golden gamma run through the variant-13 finaliser (mod 2^64)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(i, dtype=np.uint64) + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def splitmix_uniform(seed, i):
+    """Top 24 bits of splitmix64 as a uniform number in [-1, 1)."""
+    return (splitmix64(seed, i) >> np.uint64(40)).astype(np.float64) / 2.0 ** 23 - 1.0
+
+
+def normalise(eta, u, v, H, mask, mean, std, noise_amp=0.0, noise_seed=0):
+    """The 5 input channels (eta, u, v, H, mask), each shifted and scaled: (x - mean) / std,
+    plus (training only) noise_amp * U on channels 0..2, U = splitmix_uniform(seed, 3 p + c)
+    for the row-major pixel index p."""
     x = np.stack([_f64(eta), _f64(u), _f64(v), _f64(H), _f64(mask)])
-    return (x - _f64(mean)[:, None, None]) / _f64(std)[:, None, None]
+    y = (x - _f64(mean)[:, None, None]) / _f64(std)[:, None, None]
+    if noise_amp > 0.0:
+        H_, W_ = y.shape[1:]
+        p = np.arange(H_ * W_, dtype=np.uint64).reshape(H_, W_)
+        for c in range(3):
+            y[c] += noise_amp * splitmix_uniform(noise_seed, p * np.uint64(3) + np.uint64(c))
+    return y
 
 
 def apply_correction(eta, u, v, out, t_std, mask):

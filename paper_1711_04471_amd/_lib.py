@@ -67,7 +67,8 @@ SIGNATURES = {
     "sw2d_batch_destroy": (ctypes.c_int, [_vp]),
     # surrogate building blocks
     "sw2d_restrict4": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 + [_vp] * 6),
-    "sw2d_pack_input": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 + [_fp, _fp, _vp, _vp]),
+    "sw2d_pack_input": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 +
+                        [_fp, _fp, ctypes.c_float, ctypes.c_uint64, _vp, _vp]),
     "sw2d_conv3x3_fwd": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp] +
                          [ctypes.c_int32] * 3 + [_vp]),
     "sw2d_conv3x3_dgrad": (ctypes.c_int, [_vp] * 4 + [ctypes.c_int32] * 3 + [_vp]),
@@ -75,8 +76,11 @@ SIGNATURES = {
     "sw2d_conv3x3_wgrad": (ctypes.c_int, [_vp, ctypes.c_int32, _vp] + [ctypes.c_int32] * 3 +
                            [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "sw2d_mse_workspace_bytes": (ctypes.c_size_t, []),
-    "sw2d_mse_grad": (ctypes.c_int, [_vp] * 3 + [ctypes.c_int32] * 3 +
+    "sw2d_mse_grad": (ctypes.c_int, [_vp, _vp, _fp, _vp] + [ctypes.c_int32] * 3 +
                       [ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "sw2d_sub3": (ctypes.c_int, [_vp] * 6 + [ctypes.c_int32, _vp, _vp]),
+    "sw2d_moments_workspace_bytes": (ctypes.c_size_t, []),
+    "sw2d_moments": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_size_t, _vp]),
     "sw2d_adam": (ctypes.c_int, [_vp] * 4 + [ctypes.c_int32] * 2 + [ctypes.c_float] * 4 + [_vp]),
     "sw2d_cast_weights": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
     "sw2d_apply_correction": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 + [_fp, _vp]),

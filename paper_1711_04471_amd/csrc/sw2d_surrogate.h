@@ -12,6 +12,8 @@ enum : int { kConvRelu = 0, kConvLinear3 = 1, kConvDgradMask = 2 };
 struct InputNorm {
     float mean[5];
     float inv_std[5];
+    float noise_amp;      // uniform noise in [-amp, amp) added to the normalised eta, u, v (training)
+    uint64_t noise_seed;  // counter-based generator key
 };
 
 struct AdamHyper {
@@ -32,8 +34,12 @@ int wgrad_chunks(int nimg, int H, int W);
 hipError_t launch_wgrad(int kin, const uint16_t* x, const uint16_t* dy, int nimg, int H, int W, float* part_w,
                         float* part_b, float* dW, float* db, hipStream_t s);
 hipError_t launch_mse_grad(const float* out, const float* target, const uint8_t* mask, int nimg, int H, int W,
-                           float inv_n, uint16_t* d_out, double* partial, int nblocks, double* loss,
-                           hipStream_t s);
+                           float inv_n, const float* tscale, uint16_t* d_out, double* partial, int nblocks,
+                           double* loss, hipStream_t s);
+hipError_t launch_sub3(const float* a0, const float* a1, const float* a2, const float* b0, const float* b1,
+                       const float* b2, int n, float* out, hipStream_t s);
+hipError_t launch_moments(const float* x, const uint8_t* mask, int64_t n, double* partial, int nblocks, double* out,
+                          hipStream_t s);
 hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int n, const AdamHyper& hp,
                        hipStream_t s);
 hipError_t launch_cast_weights(const float* master, int kin, int dkin, uint16_t* wk, uint16_t* wd, hipStream_t s);

@@ -86,6 +86,16 @@ __global__ __launch_bounds__(256) void restrict4_kernel(const float* __restrict_
 }
 
 // ------------------------------------------------------------------------------ pack_input
+// SplitMix64 (Steele, Lea & Flood, 2014) of the counter seed + (i + 1) * golden gamma, mapped
+// to a uniform float in [-1, 1): the training-noise generator, keyed by (seed, element).
+__device__ __forceinline__ float splitmix_uniform(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (float)(z >> 40) * (1.0f / 8388608.0f) - 1.0f;
+}
+
 __global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict__ eta, const float* __restrict__ u,
                                                          const float* __restrict__ v, const float* __restrict__ H,
                                                          const uint8_t* __restrict__ mask, int npix, InputNorm nrm,
@@ -97,7 +107,11 @@ __global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict
 #pragma unroll
     for (int c = 0; c < 16; ++c) o[c] = 0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) o[c] = f2bf((x[c] - nrm.mean[c]) * nrm.inv_std[c]);
+    for (int c = 0; c < 5; ++c) {
+        float y = (x[c] - nrm.mean[c]) * nrm.inv_std[c];
+        if (c < 3 && nrm.noise_amp > 0.f) y += nrm.noise_amp * splitmix_uniform(nrm.noise_seed, (uint64_t)p * 3 + c);
+        o[c] = f2bf(y);
+    }
     uint4* dst = reinterpret_cast<uint4*>(out + (size_t)p * 16);
     uint4 a, b;
     a.x = o[0] | ((uint32_t)o[1] << 16);
@@ -363,8 +377,9 @@ __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restri
 // partial[block] = sum act (out - target)^2.
 __global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__ out, const float* __restrict__ target,
                                                        const uint8_t* __restrict__ mask, int nimg, int H, int W,
-                                                       float inv_n, uint16_t* __restrict__ d_out,
-                                                       double* __restrict__ partial) {
+                                                       float inv_n, float ts0, float ts1, float ts2,
+                                                       uint16_t* __restrict__ d_out, double* __restrict__ partial) {
+    const float tscale[3] = {ts0, ts1, ts2};
     __shared__ double lds[256];
     const size_t npix = (size_t)nimg * H * W;
     double s = 0.0;
@@ -379,7 +394,7 @@ __global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const size_t f = (img * 3 + c) * H * W + pin;
-            const float r = act[c] ? out[f] - target[f] : 0.f;
+            const float r = act[c] ? out[f] - target[f] * tscale[c] : 0.f;
             s += (double)r * (double)r;
             o[c] = f2bf(2.f * r * inv_n);
         }
@@ -477,7 +492,87 @@ __global__ __launch_bounds__(256) void sqdiff_kernel(const float* __restrict__ a
     if (threadIdx.x == 0) partial[blockIdx.x] = lds[0];
 }
 
+// ------------------------------------------------------------------------------ sub3
+// out[c][p] = a_c[p] - b_c[p] for the three fields (training target: fine ahead minus coarse).
+__global__ __launch_bounds__(256) void sub3_kernel(const float* __restrict__ a0, const float* __restrict__ a1,
+                                                   const float* __restrict__ a2, const float* __restrict__ b0,
+                                                   const float* __restrict__ b1, const float* __restrict__ b2,
+                                                   int n, float* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    out[p] = a0[p] - b0[p];
+    out[(size_t)n + p] = a1[p] - b1[p];
+    out[2 * (size_t)n + p] = a2[p] - b2[p];
+}
+
+// ------------------------------------------------------------------------------ moments
+// partial[block] = (sum x, sum x^2) in double over entries with mask != 0 (all if no mask).
+__global__ __launch_bounds__(256) void moments_kernel(const float* __restrict__ x, const uint8_t* __restrict__ mask,
+                                                      int64_t n, double* __restrict__ partial) {
+    __shared__ double l1[256], l2[256];
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        if (!mask || mask[i]) {
+            const double v = (double)x[i];
+            s1 += v;
+            s2 += v * v;
+        }
+    l1[threadIdx.x] = s1;
+    l2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            l1[threadIdx.x] += l1[threadIdx.x + h];
+            l2[threadIdx.x] += l2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = l1[0];
+        partial[2 * blockIdx.x + 1] = l2[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void moments_final_kernel(const double* __restrict__ partial, int n,
+                                                            double* __restrict__ out) {
+    __shared__ double l1[256], l2[256];
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        s1 += partial[2 * i];
+        s2 += partial[2 * i + 1];
+    }
+    l1[threadIdx.x] = s1;
+    l2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            l1[threadIdx.x] += l1[threadIdx.x + h];
+            l2[threadIdx.x] += l2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = l1[0];
+        out[1] = l2[0];
+    }
+}
+
 // ------------------------------------------------------------------------------ launchers
+hipError_t launch_sub3(const float* a0, const float* a1, const float* a2, const float* b0, const float* b1,
+                       const float* b2, int n, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(sub3_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a0, a1, a2, b0, b1, b2, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const float* x, const uint8_t* mask, int64_t n, double* partial, int nblocks, double* out,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(moments_kernel, dim3(nblocks), dim3(256), 0, s, x, mask, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_restrict4(const float* eta, const float* u, const float* v, const float* H,
                             const uint8_t* mask, int NX, int NY, float* eta_c, float* u_c, float* v_c,
                             float* H_c, uint8_t* mask_c, hipStream_t s) {
@@ -536,10 +631,10 @@ hipError_t launch_wgrad(int kin, const uint16_t* x, const uint16_t* dy, int nimg
 }
 
 hipError_t launch_mse_grad(const float* out, const float* target, const uint8_t* mask, int nimg, int H, int W,
-                           float inv_n, uint16_t* d_out, double* partial, int nblocks, double* loss,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(mse_grad_kernel, dim3(nblocks), dim3(256), 0, s, out, target, mask, nimg, H, W, inv_n, d_out,
-                       partial);
+                           float inv_n, const float* tscale, uint16_t* d_out, double* partial, int nblocks,
+                           double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(nblocks), dim3(256), 0, s, out, target, mask, nimg, H, W, inv_n,
+                       tscale[0], tscale[1], tscale[2], d_out, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partial, nblocks, loss);

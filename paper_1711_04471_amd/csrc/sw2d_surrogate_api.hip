@@ -45,10 +45,13 @@ int sw2d_restrict4(const float* eta, const float* u, const float* v, const float
 }
 
 int sw2d_pack_input(const float* eta, const float* u, const float* v, const float* H, const uint8_t* mask,
-                    int32_t nx, int32_t ny, const float* mean, const float* std_, uint16_t* out, void* stream) {
+                    int32_t nx, int32_t ny, const float* mean, const float* std_, float noise_amp, uint64_t noise_seed,
+                    uint16_t* out, void* stream) {
     if (!eta || !u || !v || !H || !mask || !mean || !std_ || !out || !aligned16(out)) return SW2D_EINVAL;
-    if (!dims_ok(1, ny, nx)) return SW2D_EINVAL;
+    if (!dims_ok(1, ny, nx) || !(noise_amp >= 0.f) || !std::isfinite(noise_amp)) return SW2D_EINVAL;
     InputNorm nrm;
+    nrm.noise_amp = noise_amp;
+    nrm.noise_seed = noise_seed;
     for (int c = 0; c < 5; ++c) {
         if (!(std_[c] > 0.f) || !std::isfinite(mean[c])) return SW2D_EINVAL;
         nrm.mean[c] = mean[c];
@@ -101,15 +104,35 @@ int sw2d_conv3x3_wgrad(const uint16_t* x, int32_t cin, const uint16_t* dy, int32
 
 size_t sw2d_mse_workspace_bytes(void) { return kMseBlocks * sizeof(double); }
 
-int sw2d_mse_grad(const float* out, const float* target, const uint8_t* mask, int32_t nimg, int32_t ny,
-                  int32_t nx, float inv_n, uint16_t* d_out, double* loss_sum, void* work, size_t work_bytes,
-                  void* stream) {
-    if (!out || !target || !mask || !d_out || !loss_sum || !work || !aligned16(d_out)) return SW2D_EINVAL;
+int sw2d_mse_grad(const float* out, const float* target, const float* target_scale, const uint8_t* mask,
+                  int32_t nimg, int32_t ny, int32_t nx, float inv_n, uint16_t* d_out, double* loss_sum, void* work,
+                  size_t work_bytes, void* stream) {
+    if (!out || !target || !target_scale || !mask || !d_out || !loss_sum || !work || !aligned16(d_out))
+        return SW2D_EINVAL;
     if (!dims_ok(nimg, ny, nx) || !(inv_n >= 0.f) || !std::isfinite(inv_n)) return SW2D_EINVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(target_scale[c])) return SW2D_EINVAL;
     if (work_bytes < sw2d_mse_workspace_bytes()) return SW2D_ENOSPC;
-    return fail(launch_mse_grad(out, target, mask, nimg, ny, nx, inv_n, d_out, static_cast<double*>(work),
-                                kMseBlocks, loss_sum, static_cast<hipStream_t>(stream)),
+    return fail(launch_mse_grad(out, target, mask, nimg, ny, nx, inv_n, target_scale, d_out,
+                                static_cast<double*>(work), kMseBlocks, loss_sum, static_cast<hipStream_t>(stream)),
                 "sw2d_mse_grad");
+}
+
+int sw2d_sub3(const float* a0, const float* a1, const float* a2, const float* b0, const float* b1, const float* b2,
+              int32_t n, float* out, void* stream) {
+    if (!a0 || !a1 || !a2 || !b0 || !b1 || !b2 || !out || n < 1) return SW2D_EINVAL;
+    return fail(launch_sub3(a0, a1, a2, b0, b1, b2, n, out, static_cast<hipStream_t>(stream)), "sw2d_sub3");
+}
+
+size_t sw2d_moments_workspace_bytes(void) { return 2 * kRmseBlocks * sizeof(double); }
+
+int sw2d_moments(const float* x, const uint8_t* mask, int64_t n, double* out2, void* work, size_t work_bytes,
+                 void* stream) {
+    if (!x || !out2 || !work || n < 1) return SW2D_EINVAL;
+    if (work_bytes < sw2d_moments_workspace_bytes()) return SW2D_ENOSPC;
+    return fail(launch_moments(x, mask, n, static_cast<double*>(work), kRmseBlocks, out2,
+                               static_cast<hipStream_t>(stream)),
+                "sw2d_moments");
 }
 
 int sw2d_adam(float* theta, const float* grad, float* m, float* v, int32_t n, int32_t t, float lr, float beta1,

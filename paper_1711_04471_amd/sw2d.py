@@ -29,6 +29,8 @@ def ring_capacity() -> int:
 
 
 def _dev_tensor(a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
     t = torch.as_tensor(np.ascontiguousarray(a))
     return t.to(device=device, dtype=dtype).contiguous()
 

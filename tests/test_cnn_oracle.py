@@ -190,3 +190,11 @@ def test_rmse_and_correction():
     assert e[2, 2] == 1.0 and e[0, 0] == 0.0
     assert u[2, 2] == 2.0 and u[2, 4] == 0.0  # east neighbour of (2, 4) is land
     assert v[2, 2] == 3.0 and v[3, 2] == 0.0
+
+
+def test_splitmix64_published_outputs():
+    # the first three outputs of SplitMix64 for seed 0, as published with the generator
+    got = [int(x) for x in cnn_ref.splitmix64(0, np.arange(3))]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    u = cnn_ref.splitmix_uniform(12345, np.arange(200000))
+    assert u.min() >= -1.0 and u.max() < 1.0 and abs(u.mean()) < 0.01 and abs(u.var() - 1 / 3) < 0.01

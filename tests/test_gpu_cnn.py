@@ -80,7 +80,8 @@ def test_restrict4(rng):
         assert np.array_equal(got.cpu().numpy() != 0, want != 0)
 
 
-def test_pack_input(rng):
+@pytest.mark.parametrize("noise", [0.0, 0.05])
+def test_pack_input(rng, noise):
     H, W = 21, 37
     fields = [rng.standard_normal((H, W)).astype(np.float32) for _ in range(4)]
     mask = (rng.uniform(size=(H, W)) < 0.7).astype(np.uint8)
@@ -90,11 +91,14 @@ def test_pack_input(rng):
     out = torch.empty((H, W, 16), dtype=torch.bfloat16, device=DEV)
     mp = mean.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
     sp = std.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-    check(lib().sw2d_pack_input(*map(ptr, g), W, H, mp, sp, ptr(out), stream()))
-    ref = cnn_ref.normalise(*fields, mask, mean, std)
+    seed = 0x1234ABCD5678
+    check(lib().sw2d_pack_input(*map(ptr, g), W, H, mp, sp, ctypes.c_float(noise), ctypes.c_uint64(seed),
+                                ptr(out), stream()))
+    ref = cnn_ref.normalise(*fields, mask, mean, std, noise_amp=noise, noise_seed=seed)
     got = out.float().cpu().numpy()
-    want = torch.from_numpy(np.transpose(ref, (1, 2, 0)).astype(np.float32)).to(torch.bfloat16).float().numpy()
-    np.testing.assert_array_equal(got[..., :5], want)
+    want = np.transpose(ref, (1, 2, 0))[..., :5]
+    # FP32 arithmetic then one BF16 rounding: within one BF16 unit of the FP64 value
+    np.testing.assert_allclose(got[..., :5], want, rtol=2 ** -7, atol=1e-6)
     assert not got[..., 5:].any()
 
 
@@ -208,17 +212,19 @@ def test_mse_grad(rng):
     loss = torch.zeros(1, dtype=torch.float64, device=DEV)
     wb = lib().sw2d_mse_workspace_bytes()
     work = torch.empty(wb, dtype=torch.uint8, device=DEV)
-    check(lib().sw2d_mse_grad(ptr(g_out), ptr(g_t), ptr(g_m), N, H, Wd, ctypes.c_float(1.0 / n_act), ptr(d),
-                              ptr(loss), ptr(work), wb, stream()))
+    scale = np.array([2.0, 0.5, 1.0], dtype=np.float32)
+    check(lib().sw2d_mse_grad(ptr(g_out), ptr(g_t), scale.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ptr(g_m),
+                              N, H, Wd, ctypes.c_float(1.0 / n_act), ptr(d), ptr(loss), ptr(work), wb, stream()))
     torch.cuda.synchronize()
     total = 0.0
     for n in range(N):
-        L, dout = cnn_ref.masked_mse(out[n], tgt[n], acts[n])
+        L, dout = cnn_ref.masked_mse(out[n], tgt[n] * scale[:, None, None].astype(np.float64), acts[n])
         total += L * acts[n].sum()
         got = np.transpose(d[n].float().cpu().numpy(), (2, 0, 1))
         np.testing.assert_allclose(got[:3], dout * acts[n].sum() / n_act, rtol=8e-3, atol=1e-6)
         assert not got[3:].any()
-    assert abs(loss.item() - total) <= 1e-9 * total
+    # r is formed in FP32 (target scaled in FP32), its squares summed in FP64
+    assert abs(loss.item() - total) <= 1e-6 * total
 
 
 def test_adam_and_casts(rng):
@@ -260,3 +266,24 @@ def test_correction_and_rmse(rng):
     torch.cuda.synchronize()
     want = cnn_ref.rmse_wet(ge.cpu().numpy(), ref, mask)
     assert abs(np.sqrt(s.item() / mask.sum()) - want) <= 1e-12 * want
+
+
+def test_sub3_and_moments(rng):
+    n = 5003
+    a = [rng.standard_normal(n).astype(np.float32) for _ in range(3)]
+    b = [rng.standard_normal(n).astype(np.float32) for _ in range(3)]
+    ga, gb = [torch.as_tensor(x).to(DEV) for x in a], [torch.as_tensor(x).to(DEV) for x in b]
+    out = torch.empty((3, n), dtype=torch.float32, device=DEV)
+    check(lib().sw2d_sub3(*map(ptr, ga), *map(ptr, gb), n, ptr(out), stream()))
+    np.testing.assert_array_equal(out.cpu().numpy(), np.stack(a) - np.stack(b))
+    mask = (rng.uniform(size=n) < 0.6).astype(np.uint8)
+    gm = torch.as_tensor(mask).to(DEV)
+    res = torch.zeros(2, dtype=torch.float64, device=DEV)
+    wb = lib().sw2d_moments_workspace_bytes()
+    work = torch.empty(wb, dtype=torch.uint8, device=DEV)
+    for m, sel in ((gm, mask != 0), (None, np.ones(n, bool))):
+        check(lib().sw2d_moments(ptr(ga[0]), ptr(m) if m is not None else None, n, ptr(res), ptr(work), wb,
+                                 stream()))
+        x = a[0][sel].astype(np.float64)
+        got = res.cpu().numpy()
+        np.testing.assert_allclose(got, [x.sum(), (x * x).sum()], rtol=1e-12)
