@@ -36,6 +36,14 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--only-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
+    ap.add_argument("--only-surrogate", action="store_true")
+    ap.add_argument("--surrogate-runs", type=int, default=20)
+    ap.add_argument("--surrogate-pairs", type=int, default=100)
+    ap.add_argument("--surrogate-epochs", type=int, default=6)
+    ap.add_argument("--surrogate-fine", type=int, default=4096)
+    ap.add_argument("--surrogate-tests", type=int, default=3)
+    ap.add_argument("--damping", type=float, default=0.5)
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy (the counter calibration)")
     return ap.parse_args()
@@ -136,6 +144,72 @@ def batched_leg(steps, warmup, log):
     }
 
 
+def surrogate_leg(args, log):
+    """The learned coarse-step surrogate: 4x-coarsened state, coarse step of 4 dt plus the
+    CNN correction, trained on snapshot pairs of plain fine runs (seeds 50000+); rollouts
+    of 500 coarse steps (2000 fine) on held-out seeds 50200+, judged every 50 coarse steps
+    by the plain fine model against a 1e-3 m eta RMSE threshold."""
+    import torch
+
+    from paper_1711_04471_amd import surrogate as S
+    from paper_1711_04471_amd.sw2d import Sw2d
+
+    n = args.surrogate_fine
+    t0 = time.perf_counter()
+    ds = S.make_dataset([50000 + k for k in range(args.surrogate_runs)], n=n, pairs_per_run=args.surrogate_pairs)
+    gen_s = time.perf_counter() - t0
+    log(f"surrogate dataset {tuple(ds.inputs.shape)} in {gen_s:.1f} s")
+    net = S.ConvNet(seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = S.Trainer(net, ds, batch=4, noise=0.05).fit(epochs=args.surrogate_epochs, lr=2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    samples = ds.samples
+    del ds
+    torch.cuda.empty_cache()
+    log(f"surrogate training {train_s:.1f} s, loss {hist}")
+    n_coarse, judge, thr = 500, 50, 1e-3
+    seeds = [50200 + k for k in range(args.surrogate_tests)]
+    per = []
+    for seed in seeds:
+        case = S.fine_basin(seed, n)
+        with Sw2d.from_case(case) as plain:
+            plain.step(10)
+            t_plain = plain.step_timed(4 * n_coarse) * 4 * n_coarse * 1e-3  # s for 2000 fine steps
+        r_cnn = S.rollout(net, case, n_coarse=n_coarse, judge_every=judge, threshold=thr, damping=args.damping)
+        r_crs = S.rollout(None, case, n_coarse=n_coarse, judge_every=judge, threshold=thr)
+        seg_plain = t_plain / (n_coarse // judge)
+        # a segment that fell back is charged at the plain model's cost of that segment
+        charged = r_cnn.surrogate_s + r_cnn.fallbacks * seg_plain
+        per.append({"seed": seed, "t_plain_s": t_plain, "t_surrogate_s": r_cnn.surrogate_s,
+                    "t_charged_s": charged, "t_judge_s": r_cnn.judge_s, "fallbacks": r_cnn.fallbacks,
+                    "fallbacks_coarse_only": r_crs.fallbacks,
+                    "rmse_cnn": [round(x, 6) for x in r_cnn.rmse],
+                    "rmse_coarse_only": [round(x, 6) for x in r_crs.rmse]})
+        log(f"surrogate seed {seed}: {per[-1]}")
+    cells = n * n
+    t_plain = sum(p["t_plain_s"] for p in per)
+    t_sur = sum(p["t_surrogate_s"] for p in per)
+    t_chg = sum(p["t_charged_s"] for p in per)
+    return {
+        "workload": f"surrogate_{n}: fine {n}^2 (4-cell border, dx=500 m) -> coarse {n // 4}^2, CNN 5-32-32-32-3 "
+                    f"3x3 BF16/FP32-acc, {samples} training pairs from {args.surrogate_runs} plain runs, "
+                    f"{args.surrogate_epochs} epochs; rollout {n_coarse} coarse steps, judge every {judge}, "
+                    f"threshold {thr} m, damping {args.damping}",
+        "value_fine_equivalent": round(cells * 4 * n_coarse * len(per) / t_chg / 1e6, 1),
+        "unit": "Mcell-steps/s (fine cells x fine steps / wall time incl. fallbacks)",
+        "speedup_vs_plain_raw": round(t_plain / t_sur, 3),
+        "speedup_vs_plain_charged": round(t_plain / t_chg, 3),
+        "fallbacks": sum(p["fallbacks"] for p in per),
+        "fallbacks_coarse_only": sum(p["fallbacks_coarse_only"] for p in per),
+        "judges": len(per) * (n_coarse // judge),
+        "mean_rmse_cnn": float(np.nanmean([x for p in per for x in p["rmse_cnn"]])),
+        "mean_rmse_coarse_only": float(np.mean([x for p in per for x in p["rmse_coarse_only"]])),
+        "train_s": round(train_s, 2), "dataset_s": round(gen_s, 2), "per_seed": per,
+    }
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -144,6 +218,9 @@ def main():
     log = lambda m: print(f"# {m}", file=sys.stderr, flush=True)
     if args.only_batched:
         print(json.dumps({"batched": batched_leg(args.batched_steps, args.warmup, log)}), flush=True)
+        return
+    if args.only_surrogate:
+        print(json.dumps({"surrogate": surrogate_leg(args, log)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -202,6 +279,8 @@ def main():
     sim.close()
     if not args.no_batched:
         out["batched"] = batched_leg(args.batched_steps, args.warmup, log)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(args, log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -93,21 +93,24 @@ def test_network_gradients_match_oracle():
         assert rel_l2(g[bo:bo + S.REAL_OUT[layer]], grads_ref[layer][1]) <= 5e-3, layer
 
 
+FINE = 1024  # a quarter of the full configuration's side: 256^2 coarse
+
+
 @pytest.fixture(scope="module")
 def small_dataset():
-    return S.make_dataset([50000 + k for k in range(6)], n=512, pairs_per_run=50)
+    return S.make_dataset([50000 + k for k in range(12)], n=FINE, pairs_per_run=100)
 
 
 @pytest.fixture(scope="module")
 def trained(small_dataset):
     net = S.ConvNet(seed=1)
-    hist = S.Trainer(net, small_dataset, batch=4, noise=0.05).fit(epochs=12, lr=2e-3)
+    hist = S.Trainer(net, small_dataset, batch=4, noise=0.05).fit(epochs=24, lr=2e-3)
     return net, hist
 
 
 def test_dataset_and_stats(small_dataset):
     ds = small_dataset
-    assert tuple(ds.inputs.shape) == (3, 300, 128, 128) and ds.targets.shape == ds.inputs.shape
+    assert tuple(ds.inputs.shape) == (3, 1200, 256, 256) and ds.targets.shape == ds.inputs.shape
     st = ds.stats
     assert np.all(st.in_std > 0) and np.all(st.t_std > 0)
     # the mask channel's mean is the water fraction of the coarse basins
@@ -131,7 +134,7 @@ def test_weights_round_trip(trained):
 
 def test_fallback_policy(trained):
     net, _ = trained
-    case = S.fine_basin(50300, 512)
+    case = S.fine_basin(50300, FINE)
     r = S.rollout(net, case, n_coarse=60, judge_every=20, threshold=0.0)
     assert r.fallbacks == 3 and len(r.rmse) == 3
     r = S.rollout(net, case, n_coarse=60, judge_every=20, threshold=1e9)
@@ -146,14 +149,16 @@ def test_fallback_policy(trained):
 
 
 def test_trained_network_gains_over_coarse_only(trained):
-    """Held-out basins: eta RMSE at the first judge (20 coarse steps) with the learned
-    correction against the coarse model alone."""
+    """Held-out basins: eta RMSE after 20 coarse steps (80 fine) from the restricted fine
+    state, with the learned (damped) correction against the coarse model alone. Measured
+    when this bar was set: ratios 0.61-0.97, mean 0.82; beyond ~50 coarse steps the gain
+    fades (reported by the benchmark, not asserted here)."""
     net, _ = trained
     ratios = []
     for seed in (50200, 50201, 50202, 50203):
-        case = S.fine_basin(seed, 512)
+        case = S.fine_basin(seed, FINE)
         base = S.rollout(None, case, n_coarse=20, judge_every=20, threshold=1e9).rmse[0]
         cnn = S.rollout(net, case, n_coarse=20, judge_every=20, threshold=1e9).rmse[0]
         ratios.append(cnn / base)
     print(json.dumps({"rmse_ratio_cnn_over_coarse": ratios}), flush=True)
-    assert np.mean(ratios) < 0.95, ratios
+    assert np.mean(ratios) < 0.92 and max(ratios) < 1.05, ratios
