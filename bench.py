@@ -70,6 +70,22 @@ def copy_probe():
                       "ms": round(ms, 4), "GBs": round(8 * n / ms / 1e6, 1)}), flush=True)
 
 
+def counter_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter record, or None
+    when the kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sw2d_step_kernel_basin_8192_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def cpu_baseline(case, target_s):
     """The FP64 oracle on the host cores: probes of 1 and 3 steps give the cost of one step
     (without the one-off conversion of the inputs), then enough steps for ~target_s."""
@@ -250,6 +266,7 @@ def main():
     cells = case.nx * case.ny
     value = cells * args.steps / wall / 1e6
     achieved = cells * BYTES_PER_CELL_STEP / (kernel_ms * 1e-3) / 1e9
+    traffic = counter_traffic() if args.workload == "basin_8192" else None
     out = {
         "metric": "Mcell-steps/s and % HBM roofline (plain vs surrogate/batched at stated RMSE)",
         "value": round(value, 1),
@@ -268,7 +285,9 @@ def main():
                                "Fourier bathymetry 5-50 m, land disks >=10%, 8 bumps",
                    "nx": case.nx, "ny": case.ny, "band_rows": sim.band_rows},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": round(traffic / 1e9, 4) if traffic else None,
+                     "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "sw2d_step_kernel", "kernel_ms": round(kernel_ms, 5),
                      "bytes_per_cell_step": BYTES_PER_CELL_STEP},
         "folds_last_step": {"vol_total": float(red["vol_total"][-1]),
