@@ -119,6 +119,23 @@ int sw2d_set_state(sw2d_t h, const float *d_eta, const float *d_u, const float *
 int sw2d_set_band_rows(sw2d_t h, int32_t rows);
 int32_t sw2d_band_rows(sw2d_t h);
 
+/* Temporal blocking: steps_per_pass = K in 2..4 makes sw2d_step advance K steps per pass
+ * over HBM (the intermediate states stay in registers; a remainder of the step count takes
+ * one shorter pass), with its own band height rows in [8, ny]; 1 (the default) restores one
+ * step per pass. The state and folds are the same as with single steps (the state bit for
+ * bit, the folds up to the order of their sums). */
+int sw2d_set_time_blocking(sw2d_t h, int32_t steps_per_pass, int32_t rows);
+int32_t sw2d_time_blocking(sw2d_t h);
+
+/* The same steps split the way the paper's compiler splits them (Sect. 6.2: three map
+ * kernels - the predictor, the Shapiro filter, the velocity update - with the folds as a
+ * separate reduction), for comparison with the fused pass: 68 B of HBM traffic per
+ * cell-step instead of 28. d_scratch: caller-owned device memory of
+ * sw2d_unfused_scratch_bytes(p) bytes (the predicted u, v and surface). The state agrees
+ * with sw2d_step to FP32 rounding. */
+size_t sw2d_unfused_scratch_bytes(const sw2d_params *p);
+int sw2d_step_unfused(sw2d_t h, int32_t nsteps, float *d_scratch, size_t scratch_bytes);
+
 /* Release the host handle. Device buffers stay the caller's. NULL is accepted. */
 int sw2d_destroy(sw2d_t h);
 

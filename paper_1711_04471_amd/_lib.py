@@ -49,6 +49,10 @@ SIGNATURES = {
     "sw2d_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64]),
     "sw2d_set_band_rows": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "sw2d_band_rows": (ctypes.c_int32, [_vp]),
+    "sw2d_unfused_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(sw2d_params)]),
+    "sw2d_step_unfused": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_size_t]),
+    "sw2d_set_time_blocking": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "sw2d_time_blocking": (ctypes.c_int32, [_vp]),
     "sw2d_destroy": (ctypes.c_int, [_vp]),
     "sw2d_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw2d_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(sw2d_params),

@@ -25,7 +25,9 @@ struct sw2d_ctx {
     sw2d_red* ring;
     FoldPartial* part;
     int part_capacity;  // partial slots per step
-    StepGeometry geo;
+    StepGeometry geo;   // one step per pass
+    StepGeometry geok[kMaxStepsPerPass + 1];  // K steps per pass (K >= 2)
+    int steps_per_pass; // 1 .. kMaxStepsPerPass
     StepCoef coef;
     int64_t step;             // steps done
     int64_t ring_first;       // first step whose fold is valid in the ring
@@ -73,8 +75,12 @@ struct Layout {
 Layout layout(const sw2d_params* p) {
     Layout L;
     const size_t cells = (size_t)p->nx * p->ny;
-    StepGeometry g = make_geometry(p->nx, p->ny, kMinRows);
-    L.part_capacity = g.nblocks;
+    int cap = 0;
+    for (int K = 1; K <= kMaxStepsPerPass; ++K) {
+        const int nb = make_geometry(p->nx, p->ny, kMinRows, strip_out_for(K)).nblocks;
+        if (nb > cap) cap = nb;
+    }
+    L.part_capacity = cap;
     size_t off = 0;
     L.hp = off;
     off = align_up(off + cells * sizeof(float));
@@ -109,10 +115,64 @@ StepCoef make_coef(const sw2d_params* p) {
     return k;
 }
 
-int flush_folds(sw2d_ctx* h, int pending) {
+int flush_folds(sw2d_ctx* h, int pending, int nparts) {
     if (pending <= 0) return SW2D_OK;
-    SW2D_HIP(launch_fold(h->part, h->geo.nblocks, h->part_capacity, pending, h->step - pending + 1,
-                         h->ring, kRingCap, h->p.dx * h->p.dy, h->h_sum, h->stream));
+    SW2D_HIP(launch_fold(h->part, nparts, h->part_capacity, pending, h->step - pending + 1, h->ring,
+                         kRingCap, h->p.dx * h->p.dy, h->h_sum, h->stream));
+    return SW2D_OK;
+}
+
+// Enqueue nsteps steps: passes of steps_per_pass steps, a single step for an odd remainder;
+// the fold partials of up to kFoldChunk steps are buffered, then added by one fold launch.
+// With events (2 per pass, at most kFoldChunk passes per chunk) the step kernels are timed.
+int enqueue_steps(sw2d_ctx* h, int32_t nsteps, hipEvent_t* ev, double* total_ms) {
+    int pending = 0, nparts = 0, passes = 0;
+    int32_t done = 0;
+    while (done < nsteps) {
+        const int k = (nsteps - done < h->steps_per_pass) ? nsteps - done : h->steps_per_pass;
+        const StepGeometry& g = (k >= 2) ? h->geok[k] : h->geo;
+        if (pending + k > kFoldChunk || (pending > 0 && g.nblocks != nparts)) {
+            int rc = flush_folds(h, pending, nparts);
+            if (rc) return rc;
+            if (ev) {
+                SW2D_HIP(hipEventSynchronize(ev[2 * passes - 1]));
+                for (int i = 0; i < passes; ++i) {
+                    float ms = 0.f;
+                    SW2D_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+                    *total_ms += ms;
+                }
+            }
+            pending = 0;
+            passes = 0;
+        }
+        float* const* src = h->state[h->cur];
+        float* const* dst = h->state[h->cur ^ 1];
+        FoldPartial* part = h->part + (size_t)pending * h->part_capacity;
+        if (ev) SW2D_HIP(hipEventRecord(ev[2 * passes], h->stream));
+        if (k >= 2)
+            SW2D_HIP(launch_stepk(k, src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part, h->part_capacity,
+                                  g, h->coef, h->stream));
+        else
+            SW2D_HIP(launch_step(src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part, g, h->coef,
+                                 h->stream));
+        if (ev) SW2D_HIP(hipEventRecord(ev[2 * passes + 1], h->stream));
+        h->cur ^= 1;
+        h->step += k;
+        pending += k;
+        nparts = g.nblocks;
+        ++passes;
+        done += k;
+    }
+    int rc = flush_folds(h, pending, nparts);
+    if (rc) return rc;
+    if (ev && passes > 0) {
+        SW2D_HIP(hipEventSynchronize(ev[2 * passes - 1]));
+        for (int i = 0; i < passes; ++i) {
+            float ms = 0.f;
+            SW2D_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+            *total_ms += ms;
+        }
+    }
     return SW2D_OK;
 }
 
@@ -159,6 +219,9 @@ int sw2d_create(const sw2d_params* p, const float* d_H, const uint8_t* d_mask, f
     h->part = reinterpret_cast<FoldPartial*>(w + L.part);
     h->part_capacity = L.part_capacity;
     h->geo = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny));
+    for (int K = 2; K <= kMaxStepsPerPass; ++K)
+        h->geok[K] = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny), strip_out_for(K));
+    h->steps_per_pass = 1;
     h->coef = make_coef(p);
     h->step = 0;
     h->ring_first = 1;
@@ -196,22 +259,7 @@ int sw2d_create(const sw2d_params* p, const float* d_H, const uint8_t* d_mask, f
 
 int sw2d_step(sw2d_t h, int32_t nsteps) {
     if (!h || nsteps < 0) return SW2D_ESTATE;
-    int pending = 0;
-    for (int32_t s = 0; s < nsteps; ++s) {
-        float* const* src = h->state[h->cur];
-        float* const* dst = h->state[h->cur ^ 1];
-        SW2D_HIP(launch_step(src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2],
-                             h->part + (size_t)pending * h->part_capacity, h->geo, h->coef,
-                             h->stream));
-        h->cur ^= 1;
-        h->step += 1;
-        if (++pending == kFoldChunk) {
-            int rc = flush_folds(h, pending);
-            if (rc) return rc;
-            pending = 0;
-        }
-    }
-    return flush_folds(h, pending);
+    return enqueue_steps(h, nsteps, nullptr, nullptr);
 }
 
 int sw2d_step_timed(sw2d_t h, int32_t nsteps, double* mean_step_ms) {
@@ -225,37 +273,7 @@ int sw2d_step_timed(sw2d_t h, int32_t nsteps, double* mean_step_ms) {
         }
     }
     double total_ms = 0.0;
-    int rc = SW2D_OK;
-    int done = 0;
-    while (done < nsteps && rc == SW2D_OK) {
-        const int n = (nsteps - done < kFoldChunk) ? nsteps - done : kFoldChunk;
-        for (int s = 0; s < n && rc == SW2D_OK; ++s) {
-            float* const* src = h->state[h->cur];
-            float* const* dst = h->state[h->cur ^ 1];
-            hipError_t e = hipEventRecord(ev[2 * s], h->stream);
-            if (e == hipSuccess)
-                e = launch_step(src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2],
-                                h->part + (size_t)s * h->part_capacity, h->geo, h->coef, h->stream);
-            if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], h->stream);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "sw2d_step_timed");
-                break;
-            }
-            h->cur ^= 1;
-            h->step += 1;
-        }
-        if (rc == SW2D_OK) rc = flush_folds(h, n);
-        if (rc == SW2D_OK) {
-            hipError_t e = hipEventSynchronize(ev[2 * n - 1]);
-            for (int s = 0; s < n && e == hipSuccess; ++s) {
-                float ms = 0.f;
-                e = hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]);
-                total_ms += ms;
-            }
-            if (e != hipSuccess) rc = hip_fail(e, "hipEventElapsedTime");
-        }
-        done += n;
-    }
+    int rc = enqueue_steps(h, nsteps, ev, &total_ms);
     for (int i = 0; i < 2 * kFoldChunk; ++i) (void)hipEventDestroy(ev[i]);
     if (rc == SW2D_OK) {
         hipError_t e = hipStreamSynchronize(h->stream);
@@ -265,12 +283,54 @@ int sw2d_step_timed(sw2d_t h, int32_t nsteps, double* mean_step_ms) {
     return rc;
 }
 
+size_t sw2d_unfused_scratch_bytes(const sw2d_params* p) {
+    if (!params_ok(p)) return 0;
+    return 3 * (size_t)p->nx * p->ny * sizeof(float);
+}
+
+int sw2d_step_unfused(sw2d_t h, int32_t nsteps, float* d_scratch, size_t scratch_bytes) {
+    if (!h || nsteps < 0 || !d_scratch) return SW2D_ESTATE;
+    if (scratch_bytes < sw2d_unfused_scratch_bytes(&h->p)) return SW2D_ENOSPC;
+    const int nparts = h->part_capacity < 1024 ? h->part_capacity : 1024;
+    int pending = 0;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        float* const* src = h->state[h->cur];
+        float* const* dst = h->state[h->cur ^ 1];
+        SW2D_HIP(launch_unfused_step(src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], d_scratch, h->p.nx,
+                                     h->p.ny, h->coef, h->part + (size_t)pending * h->part_capacity, nparts,
+                                     h->stream));
+        h->cur ^= 1;
+        h->step += 1;
+        if (++pending == kFoldChunk) {
+            int rc = flush_folds(h, pending, nparts);
+            if (rc) return rc;
+            pending = 0;
+        }
+    }
+    return flush_folds(h, pending, nparts);
+}
+
 int sw2d_set_band_rows(sw2d_t h, int32_t rows) {
     if (!h) return SW2D_ESTATE;
     if (rows < kMinRows || rows > h->p.ny) return SW2D_EINVAL;
     h->geo = make_geometry(h->p.nx, h->p.ny, rows);
     return SW2D_OK;
 }
+
+int sw2d_set_time_blocking(sw2d_t h, int32_t steps_per_pass, int32_t rows) {
+    if (!h) return SW2D_ESTATE;
+    if (steps_per_pass < 1 || steps_per_pass > kMaxStepsPerPass) return SW2D_EINVAL;
+    if (steps_per_pass >= 2) {
+        if (rows < kMinRows || rows > h->p.ny) return SW2D_EINVAL;
+        // the same band height for the shorter passes that finish a step count
+        for (int K = 2; K <= kMaxStepsPerPass; ++K)
+            h->geok[K] = make_geometry(h->p.nx, h->p.ny, rows, strip_out_for(K));
+    }
+    h->steps_per_pass = steps_per_pass;
+    return SW2D_OK;
+}
+
+int32_t sw2d_time_blocking(sw2d_t h) { return h ? h->steps_per_pass : -1; }
 
 int32_t sw2d_band_rows(sw2d_t h) { return h ? h->geo.rows : -1; }
 

@@ -11,6 +11,8 @@ namespace sw2d {
 constexpr int kWave = 64;                            // CDNA wavefront width
 constexpr int kHalo = 2;                             // stencil radius of the fused step
 constexpr int kStripOut = kWave - 2 * kHalo;         // output columns per wave strip (60)
+constexpr int kMaxStepsPerPass = 4;                 // temporal blocking depth (K steps per pass)
+constexpr int strip_out_for(int K) { return kWave - 4 * K; }  // owned columns: 60, 56, 52, 48
 #ifndef SW2D_WAVES_PER_GROUP
 #define SW2D_WAVES_PER_GROUP 4
 #endif
@@ -61,11 +63,11 @@ struct PrepFlags {
 
 constexpr int kHsumBlocks = 256;  // partials of the one-off sum_wet H
 
-inline StepGeometry make_geometry(int nx, int ny, int rows) {
+inline StepGeometry make_geometry(int nx, int ny, int rows, int strip_out = kStripOut) {
     StepGeometry g;
     g.nx = nx;
     g.ny = ny;
-    g.strips = (nx + kStripOut - 1) / kStripOut;
+    g.strips = (nx + strip_out - 1) / strip_out;
     g.groups_x = (g.strips + kWavesPerGroup - 1) / kWavesPerGroup;
     g.rows = rows;
     g.bands = (ny + rows - 1) / rows;
@@ -76,11 +78,21 @@ inline StepGeometry make_geometry(int nx, int ny, int rows) {
 hipError_t launch_step(const float* eta, const float* u, const float* v, const float* hp,
                        float* eta_o, float* u_o, float* v_o, FoldPartial* part,
                        const StepGeometry& geo, const StepCoef& k, hipStream_t s);
+// K = 2..4 steps in one pass (geometry from make_geometry(..., strip_out_for(K))); the
+// partials of step s of the pass go to part[s * stride + 0..nblocks).
+hipError_t launch_stepk(int K, const float* eta, const float* u, const float* v, const float* hp,
+                        float* eta_o, float* u_o, float* v_o, FoldPartial* part, int stride,
+                        const StepGeometry& geo, const StepCoef& k, hipStream_t s);
 // Partials of step s of the chunk start at part + s * stride; nparts of them are valid.
 hipError_t launch_fold(const FoldPartial* part, int nparts, int stride, int nsteps,
                        int64_t first_step, sw2d_red* ring, int ring_cap, double cell_area,
                        double h_sum, hipStream_t s);
 // Validation + packing, then sum_wet H; scratch holds kHsumBlocks doubles.
+// The paper-shaped split: dyn, shapiro, velocity update, then a fold over the new state
+// into part[0..nparts). scratch holds 3 nx ny floats.
+hipError_t launch_unfused_step(const float* eta, const float* u, const float* v, const float* hp, float* eta_o,
+                               float* u_o, float* v_o, float* scratch, int nx, int ny, const StepCoef& k,
+                               FoldPartial* part, int nparts, hipStream_t s);
 hipError_t launch_prep(const float* H, const uint8_t* mask, const float* eta, const float* u,
                        const float* v, int nx, int ny, float* hp, PrepFlags* flags,
                        double* scratch, hipStream_t s);

@@ -149,6 +149,51 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
     workgroup_fold(f_disp, f_mu, f_mv, part + blockIdx.x);
 }
 
+// K steps per pass over HBM (temporal blocking): strips of 64 - 4K owned columns, bands
+// with a 2K-row halo; the intermediate states stay in registers.
+template <int K>
+__global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
+    const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
+    const float* __restrict__ hp, float* __restrict__ eta_o, float* __restrict__ u_o,
+    float* __restrict__ v_o, FoldPartial* __restrict__ part, int stride, StepGeometry geo, StepCoef k) {
+    const int tile = tile_of_block(blockIdx.x, geo.nblocks);
+#if SW2D_BAND_BLOCK > 1
+    const int per_block = geo.groups_x * SW2D_BAND_BLOCK;
+    const int blk = tile / per_block;
+    const int rem = tile - blk * per_block;
+    const int nb = min(SW2D_BAND_BLOCK, geo.bands - blk * SW2D_BAND_BLOCK);
+    const int group = rem / nb;
+    const int band = blk * SW2D_BAND_BLOCK + (rem - group * nb);
+#else
+    const int band = tile / geo.groups_x;
+    const int group = tile - band * geo.groups_x;
+#endif
+    constexpr int kOut = kWave - 4 * K;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int strip = group * kWavesPerGroup + wave;
+    const int c = strip * kOut - 2 * K + lane;
+    const bool col_in = c >= 0 && c < geo.nx;
+    const bool out_lane = col_in && lane >= 2 * K && lane < kWave - 2 * K;
+    const int j0 = band * geo.rows;
+    const int j1 = min(j0 + geo.rows, geo.ny);
+
+    LaneFolds F[K];
+    if (strip < geo.strips) {
+#if SW2D_ZIGZAG
+        if (band & 1)
+            marchK<K, false>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k, F);
+        else
+#endif
+            marchK<K, true>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k, F);
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        if (s > 0) __syncthreads();
+        workgroup_fold(F[s].disp, F[s].mu, F[s].mv, part + (size_t)s * stride + blockIdx.x);
+    }
+}
+
 // Final level of the folds: one workgroup per step adds that step's partials in a
 // fixed order and writes the ring entry. h_sum = sum over water cells of H.
 __global__ __launch_bounds__(kFoldThreads) void sw2d_fold_kernel(const FoldPartial* __restrict__ part,
@@ -261,6 +306,29 @@ hipError_t launch_step(const float* eta, const float* u, const float* v, const f
                        const StepGeometry& geo, const StepCoef& k, hipStream_t s) {
     hipLaunchKernelGGL(sw2d_step_kernel, dim3(geo.nblocks), dim3(kGroupThreads), 0, s, eta, u, v, hp,
                        eta_o, u_o, v_o, part, geo, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_stepk(int K, const float* eta, const float* u, const float* v, const float* hp,
+                        float* eta_o, float* u_o, float* v_o, FoldPartial* part, int stride,
+                        const StepGeometry& geo, const StepCoef& k, hipStream_t s) {
+    const dim3 grid(geo.nblocks), block(kGroupThreads);
+    switch (K) {
+        case 2:
+            hipLaunchKernelGGL(sw2d_stepk_kernel<2>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, stride,
+                               geo, k);
+            break;
+        case 3:
+            hipLaunchKernelGGL(sw2d_stepk_kernel<3>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, stride,
+                               geo, k);
+            break;
+        case 4:
+            hipLaunchKernelGGL(sw2d_stepk_kernel<4>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, stride,
+                               geo, k);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

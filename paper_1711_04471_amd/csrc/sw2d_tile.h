@@ -104,55 +104,102 @@ __device__ __forceinline__ float shapiro(float es_c, bool w_c, bool wE, bool wW,
     return w_c ? es_c + e4 * s : 0.f;
 }
 
-// One wave marches a band [j0, j1) of its strip, north (kNorth) or south, and writes
-// the new state of its output lanes. Every output value is the same expression in
-// either direction; only the order of the per-lane fold additions differs.
+// One time step of one wave's strip as a row pipeline. push() consumes input row r (in
+// march order) and returns the new state of the row two behind it: row r gives the x-face
+// predictor, flux and partial surface update; row r-1 (r+1 marching south) its y-face and
+// the predicted surface es; row r-2 (r+2) the Shapiro filter. Every output value is the
+// same expression in either direction.
 template <bool kNorth>
-__device__ __forceinline__ void march(const float* __restrict__ eta, const float* __restrict__ u,
-                                      const float* __restrict__ v, const float* __restrict__ hp,
-                                      float* __restrict__ eta_o, float* __restrict__ u_o,
-                                      float* __restrict__ v_o, int nx, int ny, int c, bool col_in,
-                                      bool out_lane, int j0, int j1, const StepCoef& k,
-                                      double& f_disp, float& f_mu, float& f_mv) {
-    auto load = [&](const float* __restrict__ p, int r) -> float {
-        return (col_in && r >= 0 && r < ny) ? p[(size_t)r * nx + c] : 0.f;
-    };
-    auto emit = [&](int q, float eta_new, float us_q, float vs_q) {
-        if (out_lane) {
-            const size_t o = (size_t)q * nx + c;
-            store(eta_o + o, eta_new);
-            store(u_o + o, us_q);
-            store(v_o + o, vs_q);
-            f_disp += (double)eta_new;  // zero on land
-            f_mu = fmaxf(f_mu, fabsf(us_q));
-            f_mv = fmaxf(f_mv, fabsf(vs_q));
-        }
-    };
-    constexpr int step = kNorth ? 1 : -1;
-    const int r_first = kNorth ? j0 - 2 : j1 + 1;
-    const int n_rows = j1 - j0 + 4;
-
-    // registers of the rows 1, 2 and 3 behind the one being loaded (in march order)
-    float e1 = 0.f, h1 = 0.f, v1 = 0.f, pe1 = 0.f, us1 = 0.f, fy1 = 0.f, vs1 = 0.f;
+struct Stage {
+    // rows 1, 2 and 3 behind the one being consumed (in march order)
+    float e1 = 0.f, h1 = 0.f, hp1 = 0.f, v1 = 0.f, pe1 = 0.f, us1 = 0.f, fy1 = 0.f, vs1 = 0.f;
     bool w1 = false, wE1 = false, wW1 = false;
-    float es2 = 0.f, fy2 = 0.f, vs2 = 0.f, us2 = 0.f;
+    float es2 = 0.f, fy2 = 0.f, vs2 = 0.f, us2 = 0.f, hp2 = 0.f;
     bool w2 = false, wE2 = false, wW2 = false;
     float es3 = 0.f;
     bool w3 = false;
 
-    float qe[SW2D_PREFETCH], qh[SW2D_PREFETCH], qu[SW2D_PREFETCH], qv[SW2D_PREFETCH];
-#pragma unroll
-    for (int d = 0; d < SW2D_PREFETCH; ++d) {
-        const int rr = r_first + d * step;
-        const bool ok = d < n_rows;
-        qe[d] = ok ? load(eta, rr) : 0.f;
-        qh[d] = ok ? load(hp, rr) : 0.f;
-        qu[d] = ok ? load(u, rr) : 0.f;
-        qv[d] = ok ? load(v, rr) : 0.f;
+    __device__ __forceinline__ void push(float e, float hpr, float ur, float vr, const StepCoef& k,
+                                         float& eta_o, float& u_o, float& v_o, float& hp_o) {
+        const RowX X = row_x(e, hpr, ur, k);
+        if constexpr (kNorth) {
+            // y-face between rows r-1 and r, then es of row r-1, then the output row r-2
+            float vs, fy;
+            face_y(v1, e1, h1, w1, X.e, X.h, X.w, k, vs, fy);
+            const float es = w1 ? pe1 - k.ry * (fy - fy2) : 0.f;
+            eta_o = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
+            u_o = us2;
+            v_o = vs2;
+            hp_o = hp2;
+            es3 = es2;
+            w3 = w2;
+            es2 = es;
+            fy2 = fy;
+            vs2 = vs;
+            v1 = vr;
+        } else {
+            // y-face between rows r and r+1, then es of row r+1, then the output row r+2
+            float vs, fy;
+            face_y(vr, X.e, X.h, X.w, e1, h1, w1, k, vs, fy);
+            const float es = w1 ? pe1 - k.ry * (fy1 - fy) : 0.f;
+            eta_o = shapiro(es2, w2, wE2, wW2, es3, w3, es, w1, k.e4);
+            u_o = us2;
+            v_o = vs2;
+            hp_o = hp2;
+            es3 = es2;
+            w3 = w2;
+            es2 = es;
+            vs2 = vs1;
+            fy1 = fy;
+            vs1 = vs;
+        }
+        us2 = us1;
+        hp2 = hp1;
+        w2 = w1;
+        wE2 = wE1;
+        wW2 = wW1;
+        e1 = X.e;
+        h1 = X.h;
+        hp1 = hpr;
+        pe1 = X.pe;
+        us1 = X.us;
+        w1 = X.w;
+        wE1 = X.wE;
+        wW1 = X.wW;
     }
-    for (int i = 0; i < n_rows; ++i) {
-        const int r = r_first + i * step;
-        const float e = qe[0], hpr = qh[0], ur = qu[0], vr = qv[0];
+};
+
+// Loads rows of one lane's column through a prefetch queue of SW2D_PREFETCH rows.
+struct RowLoader {
+    const float* __restrict__ eta;
+    const float* __restrict__ u;
+    const float* __restrict__ v;
+    const float* __restrict__ hp;
+    int nx, ny, c;
+    bool col_in;
+    float qe[SW2D_PREFETCH], qh[SW2D_PREFETCH], qu[SW2D_PREFETCH], qv[SW2D_PREFETCH];
+
+    __device__ __forceinline__ float load(const float* __restrict__ p, int r) const {
+        return (col_in && r >= 0 && r < ny) ? p[(size_t)r * nx + c] : 0.f;
+    }
+    __device__ __forceinline__ void fill(int r_first, int step, int n_rows) {
+#pragma unroll
+        for (int d = 0; d < SW2D_PREFETCH; ++d) {
+            const int rr = r_first + d * step;
+            const bool ok = d < n_rows;
+            qe[d] = ok ? load(eta, rr) : 0.f;
+            qh[d] = ok ? load(hp, rr) : 0.f;
+            qu[d] = ok ? load(u, rr) : 0.f;
+            qv[d] = ok ? load(v, rr) : 0.f;
+        }
+    }
+    // Row i (at r) out of the queue; row i + SW2D_PREFETCH requested.
+    __device__ __forceinline__ void next(int i, int r, int step, int n_rows, float& e, float& h, float& uu,
+                                         float& vv) {
+        e = qe[0];
+        h = qh[0];
+        uu = qu[0];
+        vv = qv[0];
 #pragma unroll
         for (int d = 0; d + 1 < SW2D_PREFETCH; ++d) {
             qe[d] = qe[d + 1];
@@ -167,49 +214,98 @@ __device__ __forceinline__ void march(const float* __restrict__ eta, const float
             qu[SW2D_PREFETCH - 1] = load(u, rr);
             qv[SW2D_PREFETCH - 1] = load(v, rr);
         }
-        const RowX X = row_x(e, hpr, ur, k);
-        if constexpr (kNorth) {
-            // y-face between rows r-1 and r, then es of row r-1, then the output row r-2
-            float vs, fy;
-            face_y(v1, e1, h1, w1, X.e, X.h, X.w, k, vs, fy);
-            const float es = w1 ? pe1 - k.ry * (fy - fy2) : 0.f;
-            const float eta_new = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
-            if (i >= 4) emit(r - 2, eta_new, us2, vs2);
-            es3 = es2;
-            w3 = w2;
-            es2 = es;
-            fy2 = fy;
-            vs2 = vs;
-            us2 = us1;
-            w2 = w1;
-            wE2 = wE1;
-            wW2 = wW1;
-            v1 = vr;
-        } else {
-            // y-face between rows r and r+1, then es of row r+1, then the output row r+2
-            float vs, fy;
-            face_y(vr, X.e, X.h, X.w, e1, h1, w1, k, vs, fy);
-            const float es = w1 ? pe1 - k.ry * (fy1 - fy) : 0.f;
-            const float eta_new = shapiro(es2, w2, wE2, wW2, es3, w3, es, w1, k.e4);
-            if (i >= 4) emit(r + 2, eta_new, us2, vs2);
-            es3 = es2;
-            w3 = w2;
-            es2 = es;
-            us2 = us1;
-            vs2 = vs1;
-            w2 = w1;
-            wE2 = wE1;
-            wW2 = wW1;
-            fy1 = fy;
-            vs1 = vs;
+    }
+};
+
+// Folds of one step over this lane's owned cells.
+struct LaneFolds {
+    double disp = 0.0;
+    float mu = 0.f, mv = 0.f;
+    __device__ __forceinline__ void add(float eta_new, float u_new, float v_new) {
+        disp += (double)eta_new;  // zero on land
+        mu = fmaxf(mu, fabsf(u_new));
+        mv = fmaxf(mv, fabsf(v_new));
+    }
+};
+
+// One wave marches a band [j0, j1) of its strip, north (kNorth) or south, and writes the
+// new state of its output lanes.
+template <bool kNorth>
+__device__ __forceinline__ void march(const float* __restrict__ eta, const float* __restrict__ u,
+                                      const float* __restrict__ v, const float* __restrict__ hp,
+                                      float* __restrict__ eta_o, float* __restrict__ u_o,
+                                      float* __restrict__ v_o, int nx, int ny, int c, bool col_in,
+                                      bool out_lane, int j0, int j1, const StepCoef& k,
+                                      double& f_disp, float& f_mu, float& f_mv) {
+    constexpr int step = kNorth ? 1 : -1;
+    const int r_first = kNorth ? j0 - 2 : j1 + 1;
+    const int n_rows = j1 - j0 + 4;
+    RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    L.fill(r_first, step, n_rows);
+    Stage<kNorth> A;
+    LaneFolds F;
+    for (int i = 0; i < n_rows; ++i) {
+        const int r = r_first + i * step;
+        float e, hpr, ur, vr;
+        L.next(i, r, step, n_rows, e, hpr, ur, vr);
+        float en, un, vn, hn;
+        A.push(e, hpr, ur, vr, k, en, un, vn, hn);
+        if (i >= 4 && out_lane) {
+            const size_t o = (size_t)(r - 2 * step) * nx + c;
+            store(eta_o + o, en);
+            store(u_o + o, un);
+            store(v_o + o, vn);
+            F.add(en, un, vn);
         }
-        e1 = X.e;
-        h1 = X.h;
-        pe1 = X.pe;
-        us1 = X.us;
-        w1 = X.w;
-        wE1 = X.wE;
-        wW1 = X.wW;
+    }
+    f_disp = F.disp;
+    f_mu = F.mu;
+    f_mv = F.mv;
+}
+
+// K time steps in one pass (temporal blocking): stage k+1 steps the rows stage k has just
+// produced, so the intermediate states never leave the registers. Each step's stencil
+// reaches two more columns into the garbage of the strip edges, so owned lanes shrink to
+// 2K .. 63-2K, and bands need a 2K-row halo; the folds of every step are taken over the
+// owned cells.
+template <int K, bool kNorth>
+__device__ __forceinline__ void marchK(const float* __restrict__ eta, const float* __restrict__ u,
+                                       const float* __restrict__ v, const float* __restrict__ hp,
+                                       float* __restrict__ eta_o, float* __restrict__ u_o,
+                                       float* __restrict__ v_o, int nx, int ny, int c, bool col_in,
+                                       bool out_lane, int j0, int j1, const StepCoef& k, LaneFolds* F) {
+    constexpr int step = kNorth ? 1 : -1;
+    const int r_first = kNorth ? j0 - 2 * K : j1 + 2 * K - 1;
+    const int n_rows = j1 - j0 + 4 * K;
+    RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    L.fill(r_first, step, n_rows);
+    Stage<kNorth> S[K];
+    for (int i = 0; i < n_rows; ++i) {
+        const int r = r_first + i * step;
+        float e, hpr, ur, vr;
+        L.next(i, r, step, n_rows, e, hpr, ur, vr);
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            // stage s sees row r - 2 s (in march order) once the stages before it are primed
+            if (s > 0 && i < 4 * s) break;
+            float en, un, vn, hn;
+            S[s].push(e, hpr, ur, vr, k, en, un, vn, hn);
+            if (i < 4 * (s + 1)) break;
+            const int ro = r - 2 * (s + 1) * step;  // row of stage s's output
+            if (out_lane && ro >= j0 && ro < j1) {
+                F[s].add(en, un, vn);
+                if (s == K - 1) {
+                    const size_t o = (size_t)ro * nx + c;
+                    store(eta_o + o, en);
+                    store(u_o + o, un);
+                    store(v_o + o, vn);
+                }
+            }
+            e = en;
+            hpr = hn;
+            ur = un;
+            vr = vn;
+        }
     }
 }
 

@@ -95,6 +95,23 @@ class Sw2d:
     def band_rows(self, rows: int) -> None:
         check(_lib.load().sw2d_set_band_rows(self._handle(), int(rows)), "sw2d_set_band_rows")
 
+    def step_unfused(self, nsteps: int) -> None:
+        """The paper-shaped three-kernel split (comparison path)."""
+        lib = _lib.load()
+        if getattr(self, "_scratch", None) is None:
+            nb = lib.sw2d_unfused_scratch_bytes(ctypes.byref(self.p))
+            self._scratch = torch.empty(int(nb), dtype=torch.uint8, device=self.device)
+        check(lib.sw2d_step_unfused(self._handle(), int(nsteps), self._scratch.data_ptr(),
+                                    self._scratch.numel()), "sw2d_step_unfused")
+
+    def set_time_blocking(self, steps_per_pass: int, rows: int = 32) -> None:
+        check(_lib.load().sw2d_set_time_blocking(self._handle(), int(steps_per_pass), int(rows)),
+              "sw2d_set_time_blocking")
+
+    @property
+    def time_blocking(self) -> int:
+        return int(_lib.load().sw2d_time_blocking(self._handle()))
+
     def reduce(self, k: int = 1, allow_unstable: bool = False) -> np.ndarray:
         out = (sw2d_red * int(k))()
         rc = _lib.load().sw2d_reduce(self._handle(), out, int(k))

@@ -168,3 +168,51 @@ def test_restart_is_bitwise():
             sim.reduce(101)  # folds before the restart point are not this run's
     assert np.array_equal(e2, full[0]) and np.array_equal(u2, full[1]) and np.array_equal(v2, full[2])
     assert np.array_equal(red["step"], np.arange(101, 201))
+
+
+@pytest.mark.parametrize("spp", [2, 3, 4])
+@pytest.mark.parametrize("shape,nsteps", [((700, 530), 37), ((61, 47), 20), ((300, 1201), 9), ((1000, 70), 1)])
+def test_k_steps_per_pass_equal_single_steps(shape, nsteps, spp):
+    """Temporal blocking keeps the intermediate state in registers; every state bit equals
+    single steps, the folds agree up to summation order and with the oracle."""
+    from paper_1711_04471_amd.sw2d import Sw2d
+    nx, ny = shape
+    c = inputs.small_basin(nx, ny, seed=nx + ny, steps=nsteps)
+    ref = gpu_run(c, nsteps=nsteps)
+    ored = sw2d_ref.run_case(c, nsteps=nsteps)[3]
+    for rows in (8, 32, 64):
+        with Sw2d.from_case(c) as sim:
+            sim.set_time_blocking(spp, rows=min(rows, ny))
+            assert sim.time_blocking == spp
+            sim.step(nsteps)
+            red = sim.reduce(nsteps)
+            got = sim.state_numpy()
+        for x, y in zip(got, ref[:3]):
+            assert np.array_equal(x, y), (shape, rows)
+        assert np.array_equal(red["step"], ref[3]["step"])
+        np.testing.assert_allclose(red["vol_disp"], ref[3]["vol_disp"], rtol=1e-12, atol=1e-9 * c.dx * c.dy)
+        assert np.array_equal(red["max_abs_u"], ref[3]["max_abs_u"])
+        assert np.array_equal(red["max_abs_v"], ref[3]["max_abs_v"])
+        np.testing.assert_allclose(red["vol_disp"], ored[:, 1], rtol=TOL, atol=1e-6 * c.dx * c.dy)
+
+
+@pytest.mark.parametrize("shape", [(64, 66), (130, 257), (300, 301)])
+def test_unfused_three_kernel_split_matches_oracle(shape):
+    """The paper-shaped split (predictor, Shapiro filter, velocity update, fold) computes
+    the same step as the fused pass: oracle bar on the state and the folds, and the exact
+    land/face pattern."""
+    from paper_1711_04471_amd.sw2d import Sw2d
+    nx, ny = shape
+    c = inputs.small_basin(nx, ny, seed=nx + 3 * ny, steps=80)
+    _say(f"unfused {nx}x{ny}")
+    with Sw2d.from_case(c) as sim:
+        sim.step_unfused(c.steps)
+        red = sim.reduce(c.steps)
+        e, u, v = sim.state_numpy()
+    oe, ou, ov, ored = sw2d_ref.run_case(c)
+    _check_state(c, e, u, v, oe, ou, ov)
+    assert np.array_equal(red["step"], np.arange(1, c.steps + 1))
+    for col, k in (("vol_total", 0), ("vol_disp", 1), ("max_abs_u", 2), ("max_abs_v", 3)):
+        np.testing.assert_allclose(red[col], ored[:, k], rtol=TOL, atol=1e-6 * c.dx * c.dy, err_msg=col)
+    fe, fu, fv, _ = gpu_run(c)
+    assert max(rel_l2(e, fe), rel_l2(u, fu), rel_l2(v, fv)) <= 1e-6
