@@ -3,11 +3,13 @@
 One benchmark step = one model time step (predictor, flux-divergence surface update,
 Shapiro filter, velocity update and the per-step folds) of the 8192 x 8192 basin
 (dx = 250 m, seeded bathymetry, land disks and 8 bumps), with the state resident in HBM.
-value = nx * ny * steps / wall time, in Mcell-steps/s. The roofline object prices the
-step kernel at its algorithmic 28 B per cell-step (read eta, u, v, H; write eta, u, v)
-against MI355X's 8 TB/s, using the mean step-kernel duration from HIP events recorded
-on the library's stream inside the timed region. cpu_baseline times the FP64 oracle on
-the host cores over a bounded number of steps of the same basin.
+value = nx * ny * steps / wall time, in Mcell-steps/s. By default the step kernel advances
+3 steps per pass over the grid (temporal blocking; the state equals single steps bit for
+bit and the folds are still taken every step). The roofline object prices one launch at
+its algorithmic bytes - read eta, u, v, H and write eta, u, v once, 28 B per cell - against
+MI355X's 8 TB/s, using the mean launch duration from HIP events recorded on the library's
+stream. cpu_baseline times the FP64 oracle on the host cores over a bounded number of
+steps of the same basin.
 """
 import argparse
 import json
@@ -32,7 +34,10 @@ def parse():
     ap.add_argument("--workload", default="basin_8192", choices=["basin_8192", "basin_2048"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--band-rows", type=int, default=0)
+    ap.add_argument("--band-rows", type=int, default=0,
+                    help="band height (default: 16 for single steps, the tuned height for passes)")
+    ap.add_argument("--steps-per-pass", type=int, default=3, choices=[1, 2, 3, 4],
+                    help="time steps per pass over the grid (temporal blocking)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--only-batched", action="store_true")
@@ -70,11 +75,21 @@ def copy_probe():
                       "ms": round(ms, 4), "GBs": round(8 * n / ms / 1e6, 1)}), flush=True)
 
 
-def counter_traffic():
+# band heights measured best per workload and steps per pass (sweep of 16..128 rows)
+TUNED_ROWS = {("basin_8192", 1): 16, ("basin_8192", 2): 16, ("basin_8192", 3): 32, ("basin_8192", 4): 128,
+              ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 32}
+
+
+def kernel_name(spp):
+    return "sw2d_step_kernel" if spp == 1 else f"sw2d_stepk_kernel<{spp}>"
+
+
+def counter_traffic(spp):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter record, or None
-    when the kernel sources have changed since the counters were taken."""
+    when there is none for this kernel or its sources have changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sw2d_step_kernel_basin_8192_traffic.json")
+    tag = "sw2d_step_kernel" if spp == 1 else f"sw2d_stepk{spp}_kernel"
+    path = os.path.join(ROOT, "profiles", f"{tag}_basin_8192_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -250,9 +265,13 @@ def main():
     case = inputs.basin_8192() if args.workload == "basin_8192" else inputs.basin_2048()
     dev = torch.device("cuda:0")
     sim = Sw2d.from_case(case, device=dev)
-    if args.band_rows:
-        sim.band_rows = args.band_rows
-    print(f"# {case.name} {case.nx}x{case.ny} band_rows={sim.band_rows} warmup {args.warmup}",
+    spp = args.steps_per_pass
+    rows = args.band_rows or TUNED_ROWS[(args.workload, spp)]
+    if spp == 1:
+        sim.band_rows = rows
+    else:
+        sim.set_time_blocking(spp, rows=rows)
+    print(f"# {case.name} {case.nx}x{case.ny} steps_per_pass={spp} band_rows={rows} warmup {args.warmup}",
           file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize(dev)
@@ -261,12 +280,13 @@ def main():
     torch.cuda.synchronize(dev)
     wall = time.perf_counter() - t0
     red = sim.reduce(min(args.steps, 16))
-    # the same number of steps again with an event pair around every step kernel
-    kernel_ms = sim.step_timed(args.steps)
+    # whole passes again with an event pair around every step-kernel launch
+    timed = max(spp, args.steps - args.steps % spp)
+    launch_ms = sim.step_timed(timed) * spp
     cells = case.nx * case.ny
     value = cells * args.steps / wall / 1e6
-    achieved = cells * BYTES_PER_CELL_STEP / (kernel_ms * 1e-3) / 1e9
-    traffic = counter_traffic() if args.workload == "basin_8192" else None
+    achieved = cells * BYTES_PER_CELL_STEP / (launch_ms * 1e-3) / 1e9
+    traffic = counter_traffic(spp) if args.workload == "basin_8192" else None
     out = {
         "metric": "Mcell-steps/s and % HBM roofline (plain vs surrogate/batched at stated RMSE)",
         "value": round(value, 1),
@@ -283,13 +303,13 @@ def main():
         "config": {"workload": f"{case.name}: {case.nx}x{case.ny} cells incl. land border, "
                                f"dx={case.dx:g} m, dt={case.dt:.4f} s, eps={case.eps}, seeded "
                                "Fourier bathymetry 5-50 m, land disks >=10%, 8 bumps",
-                   "nx": case.nx, "ny": case.ny, "band_rows": sim.band_rows},
+                   "nx": case.nx, "ny": case.ny, "steps_per_pass": spp, "band_rows": rows},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(traffic / 1e9, 4) if traffic else None,
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "sw2d_step_kernel", "kernel_ms": round(kernel_ms, 5),
-                     "bytes_per_cell_step": BYTES_PER_CELL_STEP},
+                     "kernel": kernel_name(spp), "kernel_ms": round(launch_ms, 5),
+                     "steps_per_launch": spp, "bytes_per_cell_per_launch": BYTES_PER_CELL_STEP},
         "folds_last_step": {"vol_total": float(red["vol_total"][-1]),
                             "vol_disp": float(red["vol_disp"][-1]),
                             "max_abs_u": float(red["max_abs_u"][-1]),

@@ -350,6 +350,12 @@ struct BatchLayout {
 };
 
 constexpr int kMaxBatchGrid = 256 * 8;  // flag lines reserved: 8 workgroups on each of 256 CUs
+// Resident workgroups per CU that the grid may count on. The occupancy query counts vector
+// registers and LDS, but a SIMD of this family also holds at most 800 scalar registers, so a
+// kernel near 100 SGPRs fits 7 waves per SIMD even when its vector registers would allow 8;
+// a grid barrier that waits for a workgroup that never became resident would only end at
+// its deadline. 6 keeps a margin below that bound.
+constexpr int kBatchWgPerCu = 6;
 
 int rows_for(const sw2d_params& p, const int32_t* band_rows, int i) {
     int r = band_rows ? band_rows[i] : 16;
@@ -562,7 +568,7 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sw2d_batch_kernel, kBatchThreads, 0);
     if (e != hipSuccess) return fail(batch_hip_fail(e, "occupancy query"));
     if (per_cu < 1 || cus < 1) return fail(SW2D_EINVAL);
-    if (per_cu > 8) per_cu = 8;
+    if (per_cu > kBatchWgPerCu) per_cu = kBatchWgPerCu;
     b->max_grid = cus * per_cu;
     if (b->max_grid > kMaxBatchGrid) b->max_grid = kMaxBatchGrid;
     b->grid = b->max_grid;

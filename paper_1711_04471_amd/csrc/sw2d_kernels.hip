@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         if (s > 0) __syncthreads();
-        workgroup_fold(F[s].disp, F[s].mu, F[s].mv, part + (size_t)s * stride + blockIdx.x);
+        workgroup_fold(F[s].disp, F[s].mu(), F[s].mv(), part + (size_t)s * stride + blockIdx.x);
     }
 }
 

@@ -27,13 +27,19 @@ namespace sw2d {
 #ifndef SW2D_BAND_BLOCK
 #define SW2D_BAND_BLOCK 2
 #endif
+#ifndef SW2D_BUFFER_IO
+#define SW2D_BUFFER_IO 1
+#endif
+#ifndef SW2D_STEADY_UNROLL
+#define SW2D_STEADY_UNROLL 1
+#endif
 static_assert(SW2D_PREFETCH >= 1 && SW2D_PREFETCH <= 4, "prefetch depth");
 
-// Lane l receives lane l+1's value (its east neighbour); lane 63 receives 0.
+// Lane l receives lane l+1's value (its east neighbour); lane 63 receives 0 (the DPP
+// bound control writes zero where the source lane lies outside the wave).
 __device__ __forceinline__ float from_east(float x) {
 #if SW2D_DPP
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130 /* wave_shl:1 */,
-                                                      0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
 #else
     return __shfl_down(x, 1, kWave);
 #endif
@@ -42,8 +48,7 @@ __device__ __forceinline__ float from_east(float x) {
 // Lane l receives lane l-1's value (its west neighbour); lane 0 receives 0.
 __device__ __forceinline__ float from_west(float x) {
 #if SW2D_DPP
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138 /* wave_shr:1 */,
-                                                      0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138 /* wave_shr:1 */, 0xf, 0xf, true));
 #else
     return __shfl_up(x, 1, kWave);
 #endif
@@ -96,8 +101,7 @@ __device__ __forceinline__ float shapiro(float es_c, bool w_c, bool wE, bool wW,
                                          float es_s, bool w_s, float e4) {
     const float esE = from_east(es_c);
     const float esW = from_west(es_c);
-    float s = 0.f;
-    if (wE) s += esE - es_c;
+    float s = wE ? esE - es_c : 0.f;
     if (wW) s += esW - es_c;
     if (w_n) s += es_n - es_c;
     if (w_s) s += es_s - es_c;
@@ -169,6 +173,31 @@ struct Stage {
     }
 };
 
+#if SW2D_BUFFER_IO
+// Rows go through buffer resources: one per field and row, whose size is the row's bytes,
+// or zero for a row outside the grid. The hardware returns 0 for a load outside the
+// resource and drops a store there, so a lane outside the grid (its byte offset, taken
+// unsigned, lies past the row) or outside the band reads land and writes nothing, with no
+// predication in the loop. Pointers and row numbers are wave-uniform.
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dwords, gfx9 family
+constexpr unsigned kNoLane = 0x80000000u;  // a byte offset past any row
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* base, int r, int nx, int ny) {
+    const bool in = r >= 0 && r < ny;
+    const float* p = base + (ptrdiff_t)(in ? r : 0) * nx;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, in ? nx * 4 : 0, kRsrcWord3);
+}
+
+__device__ __forceinline__ float row_load(const float* base, int r, int nx, int ny, unsigned off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(row_rsrc(base, r, nx, ny), (int)off, 0, 0));
+}
+
+// off: this lane's byte offset, or kNoLane for a lane that must not write
+__device__ __forceinline__ void row_store(float* base, int r, int nx, unsigned off, float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), row_rsrc(base, r, nx, r + 1), (int)off, 0, 0);
+}
+#endif
+
 // Loads rows of one lane's column through a prefetch queue of SW2D_PREFETCH rows.
 struct RowLoader {
     const float* __restrict__ eta;
@@ -179,9 +208,15 @@ struct RowLoader {
     bool col_in;
     float qe[SW2D_PREFETCH], qh[SW2D_PREFETCH], qu[SW2D_PREFETCH], qv[SW2D_PREFETCH];
 
+#if SW2D_BUFFER_IO
+    __device__ __forceinline__ float load(const float* __restrict__ p, int r) const {
+        return row_load(p, r, nx, ny, col_in ? (unsigned)c * 4u : kNoLane);
+    }
+#else
     __device__ __forceinline__ float load(const float* __restrict__ p, int r) const {
         return (col_in && r >= 0 && r < ny) ? p[(size_t)r * nx + c] : 0.f;
     }
+#endif
     __device__ __forceinline__ void fill(int r_first, int step, int n_rows) {
 #pragma unroll
         for (int d = 0; d < SW2D_PREFETCH; ++d) {
@@ -217,15 +252,46 @@ struct RowLoader {
     }
 };
 
+// Writes one output row of the new state.
+struct RowStorer {
+    float* __restrict__ eta;
+    float* __restrict__ u;
+    float* __restrict__ v;
+    int nx, c;
+    bool out_lane;
+#if SW2D_BUFFER_IO
+    __device__ __forceinline__ void put(int r, float e, float uu, float vv) const {
+        const unsigned off = out_lane ? (unsigned)c * 4u : kNoLane;
+        row_store(eta, r, nx, off, e);
+        row_store(u, r, nx, off, uu);
+        row_store(v, r, nx, off, vv);
+    }
+#else
+    __device__ __forceinline__ void put(int r, float e, float uu, float vv) const {
+        if (out_lane) {
+            const size_t o = (size_t)r * nx + c;
+            store(eta + o, e);
+            store(u + o, uu);
+            store(v + o, vv);
+        }
+    }
+#endif
+};
+
 // Folds of one step over this lane's owned cells.
+// The maxima of |u| and |v| are kept as the bit patterns of the magnitudes, whose unsigned
+// order is the numeric order for non-negative floats: one AND and one integer max per value,
+// with no NaN canonicalisation (a NaN magnitude sorts above infinity and stays visible).
 struct LaneFolds {
     double disp = 0.0;
-    float mu = 0.f, mv = 0.f;
+    unsigned mu_bits = 0u, mv_bits = 0u;
     __device__ __forceinline__ void add(float eta_new, float u_new, float v_new) {
         disp += (double)eta_new;  // zero on land
-        mu = fmaxf(mu, fabsf(u_new));
-        mv = fmaxf(mv, fabsf(v_new));
+        mu_bits = max(mu_bits, __float_as_uint(u_new) & 0x7fffffffu);
+        mv_bits = max(mv_bits, __float_as_uint(v_new) & 0x7fffffffu);
     }
+    __device__ __forceinline__ float mu() const { return __uint_as_float(mu_bits); }
+    __device__ __forceinline__ float mv() const { return __uint_as_float(mv_bits); }
 };
 
 // One wave marches a band [j0, j1) of its strip, north (kNorth) or south, and writes the
@@ -241,6 +307,7 @@ __device__ __forceinline__ void march(const float* __restrict__ eta, const float
     const int r_first = kNorth ? j0 - 2 : j1 + 1;
     const int n_rows = j1 - j0 + 4;
     RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, step, n_rows);
     Stage<kNorth> A;
     LaneFolds F;
@@ -250,17 +317,14 @@ __device__ __forceinline__ void march(const float* __restrict__ eta, const float
         L.next(i, r, step, n_rows, e, hpr, ur, vr);
         float en, un, vn, hn;
         A.push(e, hpr, ur, vr, k, en, un, vn, hn);
-        if (i >= 4 && out_lane) {
-            const size_t o = (size_t)(r - 2 * step) * nx + c;
-            store(eta_o + o, en);
-            store(u_o + o, un);
-            store(v_o + o, vn);
-            F.add(en, un, vn);
+        if (i >= 4) {
+            W.put(r - 2 * step, en, un, vn);
+            if (out_lane) F.add(en, un, vn);
         }
     }
     f_disp = F.disp;
-    f_mu = F.mu;
-    f_mv = F.mv;
+    f_mu = F.mu();
+    f_mv = F.mv();
 }
 
 // K time steps in one pass (temporal blocking): stage k+1 steps the rows stage k has just
@@ -278,28 +342,74 @@ __device__ __forceinline__ void marchK(const float* __restrict__ eta, const floa
     const int r_first = kNorth ? j0 - 2 * K : j1 + 2 * K - 1;
     const int n_rows = j1 - j0 + 4 * K;
     RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, step, n_rows);
     Stage<kNorth> S[K];
-    for (int i = 0; i < n_rows; ++i) {
+    int i = 0;
+    // Priming: stage s starts at row 4s (march order) and has valid output from row 4(s+1).
+    for (; i < 4 * K; ++i) {
         const int r = r_first + i * step;
         float e, hpr, ur, vr;
         L.next(i, r, step, n_rows, e, hpr, ur, vr);
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            // stage s sees row r - 2 s (in march order) once the stages before it are primed
             if (s > 0 && i < 4 * s) break;
             float en, un, vn, hn;
             S[s].push(e, hpr, ur, vr, k, en, un, vn, hn);
             if (i < 4 * (s + 1)) break;
             const int ro = r - 2 * (s + 1) * step;  // row of stage s's output
-            if (out_lane && ro >= j0 && ro < j1) {
+            if (ro >= j0 && ro < j1 && out_lane) F[s].add(en, un, vn);
+            e = en;
+            hpr = hn;
+            ur = un;
+            vr = vn;
+        }
+    }
+    // Steady state: every stage has valid output; the last one's rows are the band's own.
+    auto row = [&](int ii) {
+        const int r = r_first + ii * step;
+        float e, hpr, ur, vr;
+        L.next(ii, r, step, n_rows, e, hpr, ur, vr);
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            float en, un, vn, hn;
+            S[s].push(e, hpr, ur, vr, k, en, un, vn, hn);
+            const int ro = r - 2 * (s + 1) * step;
+            if (s == K - 1) {
+                W.put(ro, en, un, vn);
+                if (out_lane) F[s].add(en, un, vn);
+            } else if (ro >= j0 && ro < j1 && out_lane) {
                 F[s].add(en, un, vn);
-                if (s == K - 1) {
-                    const size_t o = (size_t)ro * nx + c;
-                    store(eta_o + o, en);
-                    store(u_o + o, un);
-                    store(v_o + o, vn);
-                }
+            }
+            e = en;
+            hpr = hn;
+            ur = un;
+            vr = vn;
+        }
+    };
+#if SW2D_STEADY_UNROLL > 1
+    // Unrolled by hand (the DPP exchanges are convergent, so the compiler will not unroll a
+    // loop of unknown trip count), which lets the lag registers rotate by renaming.
+    for (; i + SW2D_STEADY_UNROLL <= n_rows; i += SW2D_STEADY_UNROLL) {
+#pragma unroll
+        for (int u = 0; u < SW2D_STEADY_UNROLL; ++u) row(i + u);
+    }
+    for (; i < n_rows; ++i) row(i);
+#else
+    for (; i < n_rows; ++i) {
+        const int r = r_first + i * step;
+        float e, hpr, ur, vr;
+        L.next(i, r, step, n_rows, e, hpr, ur, vr);
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            float en, un, vn, hn;
+            S[s].push(e, hpr, ur, vr, k, en, un, vn, hn);
+            const int ro = r - 2 * (s + 1) * step;
+            if (s == K - 1) {
+                W.put(ro, en, un, vn);
+                if (out_lane) F[s].add(en, un, vn);
+            } else if (ro >= j0 && ro < j1 && out_lane) {
+                F[s].add(en, un, vn);
             }
             e = en;
             hpr = hn;
@@ -307,6 +417,7 @@ __device__ __forceinline__ void marchK(const float* __restrict__ eta, const floa
             vr = vn;
         }
     }
+#endif
 }
 
 }  // namespace sw2d
