@@ -127,9 +127,10 @@ __global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict
 }
 
 // ------------------------------------------------------------------------------ conv3x3
-// Tile: kConvTH rows x 32 columns of output pixels per workgroup (4 waves, 2 rows each);
+// Tile: kConvTH rows x 32 columns of output pixels per workgroup (4 waves, TH/4 rows each);
 // the (TH+2) x 34 input patch is staged in LDS with a padded pixel stride.
 constexpr int kConvTH = 8;
+constexpr int kConvRowsPerWave = kConvTH / 4;
 constexpr int kConvTW = 32;
 constexpr int kConvThreads = 256;
 
@@ -148,34 +149,20 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
                                                                uint16_t* __restrict__ out_bf,
                                                                float* __restrict__ out_f,
                                                                const uint16_t* __restrict__ relu_src, int H,
-                                                               int W) {
+                                                               int W, int nimg) {
     using L = ConvLds<KIN>;
     __shared__ __attribute__((aligned(16))) unsigned char patch[L::kBytes];
     const int tiles_x = (W + kConvTW - 1) / kConvTW;
     const int tiles_y = (H + kConvTH - 1) / kConvTH;
-    const int tile = blockIdx.x % (tiles_x * tiles_y);
-    const int img = blockIdx.x / (tiles_x * tiles_y);
-    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    const int y0 = ty * kConvTH, x0 = tx * kConvTW;
-    const size_t img_off = (size_t)img * H * W;
-
-    // stage the input patch (zero outside the image)
-    constexpr int kChunks = KIN / 8;  // 16 B chunks per pixel
-    for (int e = threadIdx.x; e < L::kRows * L::kCols * kChunks; e += kConvThreads) {
-        const int pix = e / kChunks, ch = e - pix * kChunks;
-        const int r = pix / L::kCols, c = pix - r * L::kCols;
-        const int gy = y0 + r - 1, gx = x0 + c - 1;
-        uint4 val = make_uint4(0u, 0u, 0u, 0u);
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-            val = reinterpret_cast<const uint4*>(in + (img_off + (size_t)gy * W + gx) * KIN)[ch];
-        *reinterpret_cast<uint4*>(patch + pix * L::kStride + ch * 16) = val;
-    }
+    const int per_img = tiles_x * tiles_y;
+    const int total = per_img * nimg;
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int half = lane / 32;  // which 8-channel group of a 16-channel chunk
     const int j = lane % 32;     // pixel within the 32-column block; also the A row (n)
 
-    // A operands (weights), one per tap and 16-channel chunk: Wk[t][n = j][k0 + 8 half + 0..7]
+    // A operands (weights), one per tap and 16-channel chunk: Wk[t][n = j][k0 + 8 half + 0..7],
+    // loaded once and kept in registers while the workgroup walks its tiles
     constexpr int kK = KIN / 16;
     bf16x8 a[9][kK];
 #pragma unroll
@@ -183,61 +170,113 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
 #pragma unroll
         for (int kc = 0; kc < kK; ++kc)
             a[t][kc] = *reinterpret_cast<const bf16x8*>(Wk + ((size_t)t * 32 + j) * KIN + kc * 16 + half * 8);
-    __syncthreads();
-
-    f32x16 acc[2];
+    float bv4[4][4];
+    if constexpr (MODE == kConvRelu) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc[b][t] = 0.f;
-
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int r = wave * 2 + b;  // output row within the tile
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int ky = t / 3, kx = t - 3 * (t / 3);
-            const unsigned char* src = patch + ((r + ky) * L::kCols + (j + kx)) * L::kStride + half * 16;
-#pragma unroll
-            for (int kc = 0; kc < kK; ++kc) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(src + kc * 32);
-                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t][kc], bv, acc[b], 0, 0, 0);
-            }
-        }
+            for (int e = 0; e < 4; ++e) bv4[q][e] = bias[8 * q + 4 * half + e];
     }
 
-    // epilogue: lane holds pixel j, output channels n = 8 (q) + 4 half + (0..3), q = 0..3
+    // The next tile's input patch is fetched into registers while the current one is
+    // multiplied, then written to LDS: every load of a patch is in flight at once.
+    constexpr int kChunks = KIN / 8;  // 16 B chunks per pixel
+    constexpr int kPatchChunks = L::kRows * L::kCols * kChunks;
+    constexpr int kPer = (kPatchChunks + kConvThreads - 1) / kConvThreads;
+    uint4 pre[kPer];
+    auto fetch = [&](int tile_g) {
+        const int img = tile_g / per_img;
+        const int tile = tile_g - img * per_img;
+        const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        const int y0 = ty * kConvTH, x0 = tx * kConvTW;
+        const size_t img_off = (size_t)img * H * W;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int gy = y0 + wave * 2 + b, gx = x0 + j;
-        if (gy >= H || gx >= W) continue;
-        const size_t p = img_off + (size_t)gy * W + gx;
-        if constexpr (MODE == kConvRelu || MODE == kConvDgradMask) {
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kConvThreads;
+            const int pix = e / kChunks, ch = e - pix * kChunks;
+            const int r = pix / L::kCols, c = pix - r * L::kCols;
+            const int gy = y0 + r - 1, gx = x0 + c - 1;
+            pre[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < kPatchChunks && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                pre[q] = reinterpret_cast<const uint4*>(in + (img_off + (size_t)gy * W + gx) * KIN)[ch];
+        }
+    };
+    auto commit = [&]() {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int n0 = 8 * q + 4 * half;
-                uint16_t o[4];
-                if constexpr (MODE == kConvRelu) {
+        for (int q = 0; q < kPer; ++q) {
+            const int e = threadIdx.x + q * kConvThreads;
+            const int pix = e / kChunks, ch = e - pix * kChunks;
+            if (e < kPatchChunks) *reinterpret_cast<uint4*>(patch + pix * L::kStride + ch * 16) = pre[q];
+        }
+    };
+
+    if ((int)blockIdx.x < total) fetch(blockIdx.x);
+    for (int tile_g = blockIdx.x; tile_g < total; tile_g += gridDim.x) {
+        const int img = tile_g / per_img;
+        const int tile = tile_g - img * per_img;
+        const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        const int y0 = ty * kConvTH, x0 = tx * kConvTW;
+        const size_t img_off = (size_t)img * H * W;
+
+        __syncthreads();  // the previous tile's patch is no longer read
+        commit();
+        __syncthreads();
+        if (tile_g + (int)gridDim.x < total) fetch(tile_g + gridDim.x);
+
+        f32x16 acc[kConvRowsPerWave];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) o[e] = f2bf(fmaxf(acc[b][4 * q + e] + bias[n0 + e], 0.f));
-                } else {
-                    const uint2 m = *reinterpret_cast<const uint2*>(relu_src + p * 32 + n0);
-                    const uint16_t mv[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16),
-                                            (uint16_t)(m.y & 0xffff), (uint16_t)(m.y >> 16)};
+        for (int b = 0; b < kConvRowsPerWave; ++b)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        o[e] = (bf2f(mv[e]) > 0.f) ? f2bf(acc[b][4 * q + e]) : (uint16_t)0;
+            for (int t = 0; t < 16; ++t) acc[b][t] = 0.f;
+
+#pragma unroll
+        for (int b = 0; b < kConvRowsPerWave; ++b) {
+            const int r = wave * kConvRowsPerWave + b;  // output row within the tile
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int ky = t / 3, kx = t - 3 * (t / 3);
+                const unsigned char* src = patch + ((r + ky) * L::kCols + (j + kx)) * L::kStride + half * 16;
+#pragma unroll
+                for (int kc = 0; kc < kK; ++kc) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(src + kc * 32);
+                    acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t][kc], bv, acc[b], 0, 0, 0);
                 }
-                uint2 w;
-                w.x = o[0] | ((uint32_t)o[1] << 16);
-                w.y = o[2] | ((uint32_t)o[3] << 16);
-                *reinterpret_cast<uint2*>(out_bf + p * 32 + n0) = w;
             }
-        } else {  // kConvLinear3: channels 0..2 as FP32 planes [img][3][H][W]
-            if (half == 0) {
+        }
+
+        // epilogue: lane holds pixel j, output channels n = 8 (q) + 4 half + (0..3), q = 0..3
 #pragma unroll
-                for (int e = 0; e < 3; ++e)
-                    out_f[((size_t)img * 3 + e) * H * W + (size_t)gy * W + gx] = acc[b][e] + bias[e];
+        for (int b = 0; b < kConvRowsPerWave; ++b) {
+            const int gy = y0 + wave * kConvRowsPerWave + b, gx = x0 + j;
+            if (gy >= H || gx >= W) continue;
+            const size_t p = img_off + (size_t)gy * W + gx;
+            if constexpr (MODE == kConvRelu || MODE == kConvDgradMask) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int n0 = 8 * q + 4 * half;
+                    uint16_t o[4];
+                    if constexpr (MODE == kConvRelu) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) o[e] = f2bf(fmaxf(acc[b][4 * q + e] + bv4[q][e], 0.f));
+                    } else {
+                        const uint2 m = *reinterpret_cast<const uint2*>(relu_src + p * 32 + n0);
+                        const uint16_t mv[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16),
+                                                (uint16_t)(m.y & 0xffff), (uint16_t)(m.y >> 16)};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            o[e] = (bf2f(mv[e]) > 0.f) ? f2bf(acc[b][4 * q + e]) : (uint16_t)0;
+                    }
+                    uint2 w;
+                    w.x = o[0] | ((uint32_t)o[1] << 16);
+                    w.y = o[2] | ((uint32_t)o[3] << 16);
+                    *reinterpret_cast<uint2*>(out_bf + p * 32 + n0) = w;
+                }
+            } else {  // kConvLinear3: channels 0..2 as FP32 planes [img][3][H][W]
+                if (half == 0) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e)
+                        out_f[((size_t)img * 3 + e) * H * W + (size_t)gy * W + gx] = acc[b][e] + bias[e];
+                }
             }
         }
     }
@@ -354,20 +393,34 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
             ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
-// dW[i] = sum over chunks (in chunk order) of part[chunk][i]; one thread per weight.
-__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part_w,
-                                                           const float* __restrict__ part_b, int chunks,
-                                                           int nw, float* __restrict__ dW, float* __restrict__ db) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// dW[i] = sum over chunks of part[chunk][i], in a fixed order: a workgroup takes 32
+// weights, its 8 slices of 32 threads add the chunks k = slice (mod 8) in increasing k, and
+// the 8 slice sums are added in slice order. Entries nw .. nw+31 are the bias.
+constexpr int kRedW = 32, kRedSlices = 8;
+
+__global__ __launch_bounds__(kRedW* kRedSlices) void wgrad_reduce_kernel(const float* __restrict__ part_w,
+                                                                        const float* __restrict__ part_b,
+                                                                        int chunks, int nw, float* __restrict__ dW,
+                                                                        float* __restrict__ db) {
+    __shared__ float red[kRedSlices][kRedW];
+    const int w = threadIdx.x % kRedW, slice = threadIdx.x / kRedW;
+    const int i = blockIdx.x * kRedW + w;
+    float acc = 0.f;
     if (i < nw) {
-        float s = 0.f;
-        for (int k = 0; k < chunks; ++k) s += part_w[(size_t)k * nw + i];
-        dW[i] = s;
+        for (int k = slice; k < chunks; k += kRedSlices) acc += part_w[(size_t)k * nw + i];
     } else if (i < nw + 32) {
-        const int o = i - nw;
-        float s = 0.f;
-        for (int k = 0; k < chunks; ++k) s += part_b[(size_t)k * 32 + o];
-        db[o] = s;
+        for (int k = slice; k < chunks; k += kRedSlices) acc += part_b[(size_t)k * 32 + (i - nw)];
+    }
+    red[slice][w] = acc;
+    __syncthreads();
+    if (slice == 0) {
+        float t = red[0][w];
+#pragma unroll
+        for (int q = 1; q < kRedSlices; ++q) t += red[q][w];
+        if (i < nw)
+            dW[i] = t;
+        else if (i < nw + 32)
+            db[i - nw] = t;
     }
 }
 
@@ -590,15 +643,44 @@ hipError_t launch_pack_input(const float* eta, const float* u, const float* v, c
     return hipGetLastError();
 }
 
+// Workgroups of `kernel` the current device holds at once (CUs x occupancy), cached per
+// device and kernel; 0 when the query fails.
+int resident_groups(const void* kernel, int threads) {
+    constexpr int kDevs = 16, kSlots = 8;
+    static thread_local const void* keys[kDevs][kSlots] = {};
+    static thread_local int vals[kDevs][kSlots] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return 0;
+    for (int i = 0; i < kSlots; ++i)
+        if (keys[dev][i] == kernel) return vals[dev][i];
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) return 0;
+    const int v = cus * (per_cu > 0 ? per_cu : 1);
+    for (int i = 0; i < kSlots; ++i)
+        if (!keys[dev][i]) {
+            keys[dev][i] = kernel;
+            vals[dev][i] = v;
+            break;
+        }
+    return v;
+}
+
 hipError_t launch_conv3x3(int kin, int mode, const uint16_t* in, const uint16_t* Wk, const float* bias,
                           uint16_t* out_bf, float* out_f, const uint16_t* relu_src, int nimg, int H, int W,
                           hipStream_t s) {
-    const int tiles = ((W + kConvTW - 1) / kConvTW) * ((H + kConvTH - 1) / kConvTH);
-    const dim3 grid(tiles * nimg), block(kConvThreads);
-#define SW2D_CONV_CASE(K, M)                                                                                      \
-    if (kin == K && mode == M) {                                                                                  \
-        hipLaunchKernelGGL((conv3x3_kernel<K, M>), grid, block, 0, s, in, Wk, bias, out_bf, out_f, relu_src, H, W); \
-        return hipGetLastError();                                                                                  \
+    // A persistent grid of as many workgroups as the device holds at once: each loads the
+    // weights once and walks tiles (measured faster than a second round of workgroups).
+    const int tiles = ((W + kConvTW - 1) / kConvTW) * ((H + kConvTH - 1) / kConvTH) * nimg;
+    const dim3 block(kConvThreads);
+#define SW2D_CONV_CASE(K, M)                                                                          \
+    if (kin == K && mode == M) {                                                                      \
+        const int cap = resident_groups(reinterpret_cast<const void*>(&conv3x3_kernel<K, M>), kConvThreads); \
+        if (cap < 1) return hipErrorInvalidDeviceFunction;                                            \
+        const dim3 grid(tiles < cap ? tiles : cap);                                                   \
+        hipLaunchKernelGGL((conv3x3_kernel<K, M>), grid, block, 0, s, in, Wk, bias, out_bf, out_f, relu_src, H, \
+                           W, nimg);                                                                  \
+        return hipGetLastError();                                                                      \
     }
     SW2D_CONV_CASE(16, kConvRelu)
     SW2D_CONV_CASE(32, kConvRelu)
@@ -625,8 +707,8 @@ hipError_t launch_wgrad(int kin, const uint16_t* x, const uint16_t* dy, int nimg
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nw = 9 * 32 * kin;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((nw + 32 + 255) / 256), dim3(256), 0, s, part_w, part_b, chunks, nw,
-                       dW, db);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((nw + 32 + kRedW - 1) / kRedW), dim3(kRedW * kRedSlices), 0, s, part_w,
+                       part_b, chunks, nw, dW, db);
     return hipGetLastError();
 }
 

@@ -30,9 +30,6 @@ namespace sw2d {
 #ifndef SW2D_BUFFER_IO
 #define SW2D_BUFFER_IO 1
 #endif
-#ifndef SW2D_STEADY_UNROLL
-#define SW2D_STEADY_UNROLL 1
-#endif
 static_assert(SW2D_PREFETCH >= 1 && SW2D_PREFETCH <= 4, "prefetch depth");
 
 // Lane l receives lane l+1's value (its east neighbour); lane 63 receives 0 (the DPP
@@ -366,36 +363,6 @@ __device__ __forceinline__ void marchK(const float* __restrict__ eta, const floa
         }
     }
     // Steady state: every stage has valid output; the last one's rows are the band's own.
-    auto row = [&](int ii) {
-        const int r = r_first + ii * step;
-        float e, hpr, ur, vr;
-        L.next(ii, r, step, n_rows, e, hpr, ur, vr);
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            float en, un, vn, hn;
-            S[s].push(e, hpr, ur, vr, k, en, un, vn, hn);
-            const int ro = r - 2 * (s + 1) * step;
-            if (s == K - 1) {
-                W.put(ro, en, un, vn);
-                if (out_lane) F[s].add(en, un, vn);
-            } else if (ro >= j0 && ro < j1 && out_lane) {
-                F[s].add(en, un, vn);
-            }
-            e = en;
-            hpr = hn;
-            ur = un;
-            vr = vn;
-        }
-    };
-#if SW2D_STEADY_UNROLL > 1
-    // Unrolled by hand (the DPP exchanges are convergent, so the compiler will not unroll a
-    // loop of unknown trip count), which lets the lag registers rotate by renaming.
-    for (; i + SW2D_STEADY_UNROLL <= n_rows; i += SW2D_STEADY_UNROLL) {
-#pragma unroll
-        for (int u = 0; u < SW2D_STEADY_UNROLL; ++u) row(i + u);
-    }
-    for (; i < n_rows; ++i) row(i);
-#else
     for (; i < n_rows; ++i) {
         const int r = r_first + i * step;
         float e, hpr, ur, vr;
@@ -417,7 +384,6 @@ __device__ __forceinline__ void marchK(const float* __restrict__ eta, const floa
             vr = vn;
         }
     }
-#endif
 }
 
 }  // namespace sw2d
