@@ -66,7 +66,10 @@ struct RowX {
     bool w, wE, wW;
 };
 
+// Floating-point contraction is off in the step's arithmetic and every fused multiply-add
+// is written out, so each kernel that inlines these routines rounds alike, bit for bit.
 __device__ __forceinline__ RowX row_x(float e, float hpr, float ur, const StepCoef& k) {
+#pragma clang fp contract(off)
     RowX o;
     o.e = e;
     o.w = hpr > 0.f;
@@ -77,32 +80,35 @@ __device__ __forceinline__ RowX row_x(float e, float hpr, float ur, const StepCo
     o.wE = hpE > 0.f;
     o.wW = hpW > 0.f;
     const bool au = o.w && o.wE;
-    o.us = au ? ur - k.cx * (eE - e) : 0.f;
-    const float fx = au ? o.us * (o.us > 0.f ? o.h : hpE + eE) : 0.f;
+    o.us = au ? fmaf(-k.cx, eE - e, ur) : 0.f;
+    // an inactive face has us = 0, so its flux is 0 without a second select
+    const float fx = o.us * (o.us > 0.f ? o.h : hpE + eE);
     const float fxW = from_west(fx);
-    o.pe = e - k.rx * (fx - fxW);
+    o.pe = fmaf(-k.rx, fx - fxW, e);
     return o;
 }
 
 // The y-face between a southern cell (lo) and its northern neighbour (hi).
 __device__ __forceinline__ void face_y(float v_lo, float e_lo, float h_lo, bool w_lo, float e_hi,
                                        float h_hi, bool w_hi, const StepCoef& k, float& vs, float& fy) {
+#pragma clang fp contract(off)
     const bool av = w_lo && w_hi;
-    vs = av ? v_lo - k.cy * (e_hi - e_lo) : 0.f;
-    fy = av ? vs * (vs > 0.f ? h_lo : h_hi) : 0.f;
+    vs = av ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
+    fy = vs * (vs > 0.f ? h_lo : h_hi);  // vs = 0 on an inactive face
 }
 
 // First-order Shapiro filter of the predicted surface es_c across water neighbours
 // (east, west, north, south, always added in that order).
 __device__ __forceinline__ float shapiro(float es_c, bool w_c, bool wE, bool wW, float es_n, bool w_n,
                                          float es_s, bool w_s, float e4) {
+#pragma clang fp contract(off)
     const float esE = from_east(es_c);
     const float esW = from_west(es_c);
     float s = wE ? esE - es_c : 0.f;
     if (wW) s += esW - es_c;
     if (w_n) s += es_n - es_c;
     if (w_s) s += es_s - es_c;
-    return w_c ? es_c + e4 * s : 0.f;
+    return w_c ? fmaf(e4, s, es_c) : 0.f;
 }
 
 // One time step of one wave's strip as a row pipeline. push() consumes input row r (in
@@ -127,7 +133,7 @@ struct Stage {
             // y-face between rows r-1 and r, then es of row r-1, then the output row r-2
             float vs, fy;
             face_y(v1, e1, h1, w1, X.e, X.h, X.w, k, vs, fy);
-            const float es = w1 ? pe1 - k.ry * (fy - fy2) : 0.f;
+            const float es = w1 ? fmaf(-k.ry, fy - fy2, pe1) : 0.f;
             eta_o = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
             u_o = us2;
             v_o = vs2;
@@ -142,7 +148,7 @@ struct Stage {
             // y-face between rows r and r+1, then es of row r+1, then the output row r+2
             float vs, fy;
             face_y(vr, X.e, X.h, X.w, e1, h1, w1, k, vs, fy);
-            const float es = w1 ? pe1 - k.ry * (fy1 - fy) : 0.f;
+            const float es = w1 ? fmaf(-k.ry, fy1 - fy, pe1) : 0.f;
             eta_o = shapiro(es2, w2, wE2, wW2, es3, w3, es, w1, k.e4);
             u_o = us2;
             v_o = vs2;
