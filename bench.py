@@ -24,6 +24,13 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_CELL_STEP = 28
 HBM_PEAK_GBS = 8000.0
+# FP32 operations of one cell-step of the scheme: x-face predictor, flux and divergence
+# (10), y-face likewise (8), Shapiro filter (9), folds (3), water flags (3); an FMA counts
+# as 2, compares and maxima as 1, selects and lane exchanges not at all.
+FLOP_PER_CELL_STEP = 33
+# FP32 vector peak without packed two-wide instructions (this build emits none):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def parse():
@@ -88,9 +95,10 @@ def kernel_name(spp):
     return "sw2d_step_kernel" if spp == 1 else f"sw2d_stepk_kernel<{spp}>"
 
 
-def counter_traffic(spp):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter record, or None
-    when there is none for this kernel or its sources have changed since it was taken."""
+def counter_record(spp):
+    """The committed rocprofv3 counter record of the step kernel (HBM bytes per launch and
+    VALU activity), or None when there is none for this kernel or its sources have changed
+    since it was taken."""
     import hashlib
     tag = "sw2d_step_kernel" if spp == 1 else f"sw2d_stepk{spp}_kernel"
     path = os.path.join(ROOT, "profiles", f"{tag}_basin_8192_traffic.json")
@@ -102,7 +110,7 @@ def counter_traffic(spp):
     for src in rec["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+    return rec if h.hexdigest() == rec["source_sha256"] else None
 
 
 def cpu_baseline(case, target_s):
@@ -305,7 +313,17 @@ def main():
     cells = case.nx * case.ny
     value = cells * args.steps / wall / 1e6
     achieved = cells * BYTES_PER_CELL_STEP / (launch_ms * 1e-3) / 1e9
-    traffic = counter_traffic(spp) if args.workload == "basin_8192" else None
+    flops = cells * spp * FLOP_PER_CELL_STEP / (launch_ms * 1e-3) / 1e12
+    rec = counter_record(spp) if args.workload == "basin_8192" else None
+    traffic = rec["hbm_bytes_per_launch"] if rec else None
+    valu_busy = round(rec["valu"]["valu_busy"], 3) if rec and "valu" in rec else None
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_cell_per_launch": BYTES_PER_CELL_STEP}
+    alu = {"bound": "alu", "achieved": round(flops, 2), "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+           "frac": round(flops / VALU_PEAK_TFLOPS, 4), "flop_per_cell_step": FLOP_PER_CELL_STEP}
+    # a single step per pass is bound by HBM; several steps per pass by the vector ALUs
+    # (the counters read them busy in nearly every cycle)
+    main, other = (hbm, alu) if spp == 1 else (alu, hbm)
     out = {
         "metric": "Mcell-steps/s and % HBM roofline (plain vs surrogate/batched at stated RMSE)",
         "value": round(value, 1),
@@ -323,12 +341,12 @@ def main():
                                f"dx={case.dx:g} m, dt={case.dt:.4f} s, eps={case.eps}, seeded "
                                "Fourier bathymetry 5-50 m, land disks >=10%, 8 bumps",
                    "nx": case.nx, "ny": case.ny, "steps_per_pass": spp, "band_rows": rows},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {**main,
                      "traffic": round(traffic / 1e9, 4) if traffic else None,
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": kernel_name(spp), "kernel_ms": round(launch_ms, 5),
-                     "steps_per_launch": spp, "bytes_per_cell_per_launch": BYTES_PER_CELL_STEP},
+                     "steps_per_launch": spp, "valu_busy_counters": valu_busy,
+                     "other_bound": other},
         "folds_last_step": {"vol_total": float(red["vol_total"][-1]),
                             "vol_disp": float(red["vol_disp"][-1]),
                             "max_abs_u": float(red["max_abs_u"][-1]),

@@ -192,7 +192,7 @@ class Coarse:
                         self.v, device=self.dev)
         self.rmse_work = torch.empty(self.lib.sw2d_rmse_workspace_bytes(), dtype=torch.uint8, device=self.dev)
         self.rmse_out = torch.zeros(1, dtype=torch.float64, device=self.dev)
-        self.n_wet = int(self.mask.sum().item())
+        self.n_wet = int(np.count_nonzero(self.mask.cpu().numpy()))  # host-side count, once
 
     def restrict(self, fine: Sw2d, out=None):
         e, u, v = fine.state()
@@ -241,6 +241,7 @@ def make_dataset(seeds, n=4096, pairs_per_run=100, every=20, lead=4, device="cud
     for r, seed in enumerate(seeds):
         case = fine_basin(seed, n)
         with Sw2d.from_case(case, device=dev) as fine:
+            fine.set_time_blocking(3, rows=32)  # bitwise the same states, fewer passes
             co = Coarse(fine, case)
             Hs[r].copy_(co.H)
             masks[r].copy_(co.mask)
@@ -281,7 +282,7 @@ def _moments(x, mask=None):
     check(lib.sw2d_moments(_p(x), _p(mask) if mask is not None else None, x.numel(), _p(out), _p(work),
                            work.numel(), torch.cuda.current_stream(dev).cuda_stream), "sw2d_moments")
     s1, s2 = out.cpu().numpy()
-    n = float(mask.sum().item()) if mask is not None else float(x.numel())
+    n = float(np.count_nonzero(mask.cpu().numpy())) if mask is not None else float(x.numel())
     mean = s1 / max(n, 1.0)
     return mean, math.sqrt(max(s2 / max(n, 1.0) - mean * mean, 0.0))
 
@@ -295,9 +296,10 @@ def compute_stats(ds: Dataset) -> Stats:
     m, sd = _moments(ds.H)
     mean.append(m)
     std.append(sd)
-    m, sd = _moments(ds.mask.to(torch.float32))
-    mean.append(m)
-    std.append(sd)
+    # the mask channel holds 0 / 1: its moments are the wet fraction (host-side, once)
+    p = float(np.count_nonzero(ds.mask.cpu().numpy())) / ds.mask.numel()
+    mean.append(p)
+    std.append(math.sqrt(max(p * (1.0 - p), 0.0)))
     std = [max(x, 1e-6) for x in std]
     t_std = [max(_moments(ds.targets[c])[1], 1e-9) for c in range(3)]
     return Stats(np.array(mean, np.float32), np.array(std, np.float32), np.array(t_std, np.float32))
@@ -331,10 +333,11 @@ class Trainer:
 
     @staticmethod
     def _active(mask):
-        w = mask != 0
+        """Active entries of the three output channels (host-side count, once per run)."""
+        w = mask.cpu().numpy() != 0
         au = w[:, :-1] & w[:, 1:]
         av = w[:-1, :] & w[1:, :]
-        return int(w.sum().item() + au.sum().item() + av.sum().item())
+        return int(w.sum() + au.sum() + av.sum())
 
     def _pack(self, j, idx):
         s = self.net.stream()
