@@ -15,6 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 
 LIBS = {
     "libsw2d_oracle.so": ["sw2d_oracle.c"],
+    "libsor_oracle.so": ["sor_oracle.c"],
 }
 
 CFLAGS = ["-O3", "-march=native", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",

@@ -218,3 +218,63 @@ def lake_at_rest(nx: int, ny: int, seed: int, level: float = 0.25) -> Case:
     c = seeded_basin(f"rest_{nx}x{ny}_s{seed}", nx, ny, 500.0, seed=seed, n_bumps=0, steps=20)
     c.eta = np.where(c.mask != 0, np.float32(level), np.float32(0.0)).astype(np.float32)
     return c
+
+
+# --------------------------------------------------------------------------- pressure Poisson
+@dataclass
+class PoissonCase:
+    """A pressure Poisson problem for red-black SOR: arrays [nz][ny][nx] (float32), the
+    outermost layer of ``p0`` holds the fixed boundary values."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    omega: float
+    iters: int
+    p0: np.ndarray = field(repr=False)
+    f: np.ndarray = field(repr=False)
+
+
+def poisson_source(rng: np.random.Generator, nx: int, ny: int, nz: int, n_blobs: int = 8,
+                   noise: float = 1e-3) -> np.ndarray:
+    """Right-hand side: Gaussian blobs (amplitude U(-1, 1), sigma U(5, 20) cells in x and y,
+    U(3, 12) cells in z, centre uniform) plus uniform noise of amplitude ``noise``; zero on
+    the boundary layer."""
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    y = np.arange(ny, dtype=np.float64)[None, :, None]
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    f = np.zeros((nz, ny, nx))
+    for _ in range(n_blobs):
+        a = rng.uniform(-1.0, 1.0)
+        sx, sy, sz = rng.uniform(5.0, 20.0), rng.uniform(5.0, 20.0), rng.uniform(3.0, 12.0)
+        cx, cy, cz = rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz)
+        f += a * (np.exp(-0.5 * ((x - cx) / sx) ** 2) * np.exp(-0.5 * ((y - cy) / sy) ** 2)
+                  * np.exp(-0.5 * ((z - cz) / sz) ** 2))
+    f += noise * rng.uniform(-1.0, 1.0, size=f.shape)
+    f[0], f[-1], f[:, 0], f[:, -1], f[:, :, 0], f[:, :, -1] = 0, 0, 0, 0, 0, 0
+    return f.astype(np.float32)
+
+
+def poisson_case(nx: int, ny: int, nz: int, seed: int, iters: int = 50, omega: float = 1.7,
+                 dx: float = 4.0, dy: float = 4.0, dz: float = 2.0, boundary: float = 0.0,
+                 name: str | None = None) -> PoissonCase:
+    """p0 = 0 inside; the boundary layer holds uniform noise of amplitude ``boundary``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = poisson_source(rng, nx, ny, nz)
+    p0 = np.zeros((nz, ny, nx), dtype=np.float64)
+    if boundary > 0.0:
+        b = boundary * rng.uniform(-1.0, 1.0, size=p0.shape)
+        inner = (slice(1, -1),) * 3
+        b[inner] = 0.0
+        p0 = b
+    return PoissonCase(name or f"poisson_{nx}x{ny}x{nz}", nx, ny, nz, dx, dy, dz, omega, iters,
+                       p0.astype(np.float32), f)
+
+
+def poisson_300() -> PoissonCase:
+    """The large-eddy simulator's pressure grid: 300 x 300 x 90 cells (1.2 km x 1.2 km at
+    4 m, 2 m vertical), 50 SOR iterations."""
+    return poisson_case(300, 300, 90, seed=60, iters=50, name="poisson_300x300x90")
