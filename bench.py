@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--surrogate-fine", type=int, default=4096)
     ap.add_argument("--surrogate-tests", type=int, default=3)
     ap.add_argument("--damping", type=float, default=0.5)
+    ap.add_argument("--no-sor", action="store_true", help="skip the SOR pressure-solver leg")
+    ap.add_argument("--only-sor", action="store_true")
+    ap.add_argument("--sor-solves", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy (the counter calibration)")
     return ap.parse_args()
@@ -268,6 +271,64 @@ def surrogate_leg(args, log):
     }
 
 
+SOR_BYTES_PER_CELL_ITER = 16  # read the other colour, own colour and own f; write own colour
+
+
+def sor_leg(args, log):
+    """Red-black SOR on the large-eddy simulator's pressure grid, 300 x 300 x 90, 50
+    iterations per solve from p = 0, residual folded every iteration; the median of
+    ``--sor-solves`` solves timed with HIP events on the solver's stream. The FP64 oracle
+    solves the same problem once on the host cores for the CPU comparison."""
+    import torch
+
+    from oracle import sor_ref
+    from paper_1711_04471_amd import inputs
+    from paper_1711_04471_amd.sw2d import SorSolver
+
+    c = inputs.poisson_300()
+    solver = SorSolver.from_case(c)
+    f = torch.from_numpy(c.f).cuda()
+    p0 = torch.from_numpy(c.p0).cuda()
+    p = p0.clone()
+    for _ in range(3):
+        p.copy_(p0)
+        solver.run(p, f)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(max(1, args.sor_solves)):
+        p.copy_(p0)
+        e0.record()
+        solver.run(p, f)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    ms = times[len(times) // 2]
+    res = solver.residuals()
+    cells = c.nx * c.ny * c.nz
+    achieved = cells * SOR_BYTES_PER_CELL_ITER * c.iters / (ms * 1e-3) / 1e9
+    out = {
+        "workload": f"{c.name}: red-black SOR, {c.iters} iterations per solve from p = 0, dx=dy={c.dx:g} m, "
+                    f"dz={c.dz:g} m, omega={c.omega}, Gaussian-blob source, Dirichlet boundary layer",
+        "value": round(cells * c.iters / (ms * 1e-3) / 1e6, 1), "unit": "Mcell-iterations/s",
+        "ms_per_solve": round(ms, 4), "us_per_iteration": round(ms / c.iters * 1e3, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_cell_iteration": SOR_BYTES_PER_CELL_ITER,
+                     "basis": "whole solve incl. layout split/merge and residual folds (HIP events)"},
+        "residual_sum_r2": {"initial": float(res["sum_r2"][0]), "final": float(res["sum_r2"][-1])},
+    }
+    if not args.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        sor_ref.run(c.p0, c.f, c.iters, c.dx, c.dy, c.dz, c.omega)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": round(cells * c.iters / dt / 1e6, 1), "unit": "Mcell-iterations/s",
+                             "cores": threads, "kind": "oracle", "sample": f"one full solve, FP64, {dt:.2f} s"}
+    log(f"sor: {out['ms_per_solve']} ms per solve")
+    return out
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -279,6 +340,9 @@ def main():
         return
     if args.only_surrogate:
         print(json.dumps({"surrogate": surrogate_leg(args, log)}), flush=True)
+        return
+    if args.only_sor:
+        print(json.dumps({"sor": sor_leg(args, log)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -357,6 +421,8 @@ def main():
         out["batched"] = batched_leg(args.batched_steps, args.warmup, log)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, log)
+    if not args.no_sor:
+        out["sor"] = sor_leg(args, log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -136,6 +136,45 @@ int32_t sw2d_time_blocking(sw2d_t h);
 size_t sw2d_unfused_scratch_bytes(const sw2d_params *p);
 int sw2d_step_unfused(sw2d_t h, int32_t nsteps, float *d_scratch, size_t scratch_bytes);
 
+/* ---------------------------------------------------------------------------------------
+ * Red-black SOR for the pressure Poisson equation (the paper's second workload, Sect. 6.3:
+ * its pressure solver, successive over-relaxation, 50 iterations on 300 x 300 x 90).
+ *
+ * Arrays are [nz][ny][nx] row-major FP32 device memory; the outermost layer of cells holds
+ * fixed (Dirichlet) values that are read, never written. The equation on interior cells is
+ * cx (pE + pW - 2p) + cy (pN + pS - 2p) + cz (pU + pD - 2p) = f, c_ = 1 / spacing^2. One
+ * iteration updates every red cell ((i + j + k) even), then every black one, to
+ * p + omega (g - p) with the Gauss-Seidel value g = (cx (pE + pW) + cy (pN + pS) +
+ * cz (pU + pD) - f) / (2 (cx + cy + cz)).
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t nx, ny, nz; /* cells incl. the boundary layer, each >= 3, product < 2^31 */
+    double dx, dy, dz;  /* spacings > 0 */
+    double omega;       /* relaxation factor, 0 < omega < 2 */
+} sw2d_sor_params;
+
+/* Residual r = f - L p of the state after `iter` iterations (iter 0 = the initial state):
+ * sum over interior cells of r^2 (FP64, fixed summation order) and max |r|. 16 bytes. */
+typedef struct {
+    int32_t iter;
+    float max_abs_r;
+    double sum_r2;
+} sw2d_sor_res;
+
+/* Device workspace for sw2d_sor_run with `iters` iterations (residual partials); 0 for
+ * invalid parameters. */
+size_t sw2d_sor_workspace_bytes(const sw2d_sor_params *p, int32_t iters);
+
+/* Run `iters` iterations on d_p in place (asynchronous on `stream`, a hipStream_t or NULL).
+ * d_f: the right-hand side (its boundary layer is not read). d_res: NULL, or device memory
+ * for iters + 1 sw2d_sor_res entries, the residual after 0, 1, ..., iters iterations.
+ * d_work: caller-owned device memory of sw2d_sor_workspace_bytes(p, iters) bytes. All
+ * buffers stay the caller's. Returns SW2D_EINVAL for invalid parameters or NULL arrays,
+ * SW2D_ENOSPC for a short workspace, SW2D_EHIP for a launch error. Deterministic: the same
+ * inputs give the same bits. */
+int sw2d_sor_run(const sw2d_sor_params *p, float *d_p, const float *d_f, int32_t iters, sw2d_sor_res *d_res,
+                 void *d_work, size_t work_bytes, void *stream);
+
 /* Release the host handle. Device buffers stay the caller's. NULL is accepted. */
 int sw2d_destroy(sw2d_t h);
 

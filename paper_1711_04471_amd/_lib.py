@@ -31,6 +31,16 @@ class sw2d_red(ctypes.Structure):
 
 assert ctypes.sizeof(sw2d_red) == 32
 
+class sw2d_sor_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("omega", ctypes.c_double)]
+
+
+class sw2d_sor_res(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("max_abs_r", ctypes.c_float), ("sum_r2", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _pp = ctypes.POINTER(ctypes.c_void_p)
 _fp = ctypes.POINTER(ctypes.c_float)
@@ -49,6 +59,9 @@ SIGNATURES = {
     "sw2d_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64]),
     "sw2d_set_band_rows": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "sw2d_band_rows": (ctypes.c_int32, [_vp]),
+    "sw2d_sor_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(sw2d_sor_params), ctypes.c_int32]),
+    "sw2d_sor_run": (ctypes.c_int, [ctypes.POINTER(sw2d_sor_params), _vp, _vp, ctypes.c_int32, _vp, _vp,
+                                    ctypes.c_size_t, _vp]),
     "sw2d_unfused_scratch_bytes": (ctypes.c_size_t, [ctypes.POINTER(sw2d_params)]),
     "sw2d_step_unfused": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_size_t]),
     "sw2d_set_time_blocking": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),

@@ -16,7 +16,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsw2d.so")
 
 SOURCES = ["sw2d_kernels.hip", "sw2d_api.hip", "sw2d_batch.hip", "sw2d_surrogate.hip",
-           "sw2d_surrogate_api.hip", "sw2d_unfused.hip"]
+           "sw2d_surrogate_api.hip", "sw2d_unfused.hip", "sw2d_sor.hip"]
 
 ARCH = "gfx950"
 HIPFLAGS = [

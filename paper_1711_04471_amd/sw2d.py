@@ -274,3 +274,43 @@ class Sw2dBatch:
             self.close()
         except Exception:
             pass
+
+
+SOR_RES_DTYPE = np.dtype([("iter", np.int32), ("max_abs_r", np.float32), ("sum_r2", np.float64)])
+
+
+class SorSolver:
+    """Red-black SOR for the pressure Poisson equation on a [nz][ny][nx] FP32 grid (the
+    boundary layer holds fixed values). Owns the workspace and residual buffer for a given
+    iteration count; ``run`` updates ``p`` in place on the current torch stream."""
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, omega, iters, device="cuda"):
+        self.lib = _lib.load()
+        self.dev = torch.device(device)
+        if self.dev.type == "cuda" and self.dev.index is None:
+            self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.p = _lib.sw2d_sor_params(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(omega))
+        self.iters = int(iters)
+        nb = self.lib.sw2d_sor_workspace_bytes(ctypes.byref(self.p), self.iters)
+        if nb == 0:
+            raise ValueError("invalid SOR parameters")
+        self.work = torch.empty(int(nb), dtype=torch.uint8, device=self.dev)
+        self.res = torch.empty((self.iters + 1) * SOR_RES_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
+
+    @classmethod
+    def from_case(cls, case, device="cuda"):
+        return cls(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.omega, case.iters, device=device)
+
+    def run(self, p: torch.Tensor, f: torch.Tensor, residuals=True) -> None:
+        for t in (p, f):
+            if t.device != self.dev or t.dtype != torch.float32 or not t.is_contiguous() or \
+                    t.numel() != self.p.nx * self.p.ny * self.p.nz:
+                raise ValueError("p and f must be contiguous float32 [nz][ny][nx] tensors on the solver's device")
+        s = torch.cuda.current_stream(self.dev).cuda_stream
+        check(self.lib.sw2d_sor_run(ctypes.byref(self.p), p.data_ptr(), f.data_ptr(), self.iters,
+                                    self.res.data_ptr() if residuals else None, self.work.data_ptr(),
+                                    self.work.numel(), s), "sw2d_sor_run")
+
+    def residuals(self) -> np.ndarray:
+        """(iter, max_abs_r, sum_r2) after 0..iters iterations of the last run (synchronises)."""
+        return self.res.cpu().numpy().view(SOR_RES_DTYPE)

@@ -59,3 +59,24 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(OSError, match="no CPU fallback"):
         _lib.load()
+
+
+def test_sor_argument_checks_need_no_gpu():
+    """Invalid SOR parameters are refused on the host before any device call."""
+    import ctypes
+
+    from paper_1711_04471_amd import _lib
+    lib = _lib.load()
+    bad = [(2, 5, 5, 1.0, 1.0, 1.0, 1.5), (5, 5, 5, 0.0, 1.0, 1.0, 1.5), (5, 5, 5, 1.0, 1.0, 1.0, 2.0),
+           (5, 5, 5, 1.0, 1.0, 1.0, 0.0), (5, 5, 5, 1.0, float("nan"), 1.0, 1.0)]
+    for args in bad:
+        p = _lib.sw2d_sor_params(*args)
+        assert lib.sw2d_sor_workspace_bytes(ctypes.byref(p), 10) == 0
+        assert lib.sw2d_sor_run(ctypes.byref(p), None, None, 10, None, None, 0, None) == -1
+    good = _lib.sw2d_sor_params(300, 300, 90, 4.0, 4.0, 2.0, 1.7)
+    nb = lib.sw2d_sor_workspace_bytes(ctypes.byref(good), 50)
+    assert nb > 0
+    assert lib.sw2d_sor_workspace_bytes(ctypes.byref(good), -1) == 0
+    # a short workspace is refused before any launch
+    assert lib.sw2d_sor_run(ctypes.byref(good), ctypes.c_void_p(16), ctypes.c_void_p(16), 50, None,
+                            ctypes.c_void_p(16), nb - 1, None) == -5
