@@ -23,6 +23,14 @@
  *  - shapiro (first-order, five-point, only across active faces):
  *        eta' = es + (eps/4) * sum over water neighbours (es_nb - es)
  *  - velocity update: u' = us, v' = vs.
+ *  - model variants (flags; a reading of the textbook family the paper's model comes
+ *    from, none of them in the paper): quadratic bottom friction on the predictor,
+ *        us = (u - (g dt/dx)(eta_E - eta)) / (1 + dt cd |u| / h_face),
+ *    h_face = mean total depth of the face's two cells (old surface, old |u|), vs
+ *    likewise; and the Shapiro filter applied to the predicted velocities as well,
+ *        u' = us + (eps/4) * sum over active neighbouring u faces (us_nb - us)
+ *    (neighbours east, west, north, south), v' likewise, after the surface update
+ *    used the unfiltered us, vs.
  *  - Per-step folds: V_disp = dx dy sum_wet eta', V_tot = dx dy sum_wet (H + eta'),
  *    max|u'|, max|v'|. The paper's compiler turns loop nests into maps and
  *    these reductions into folds (Sect. 4.3).
@@ -46,14 +54,48 @@ static int is_wet(const unsigned char *mask, int nx, int ny, int j, int i) {
     return AT(mask, j, i) != 0;
 }
 
-/* One step. scratch holds 3*nx*ny doubles (Fx, Fy, es). Returns 0, or 1 if a
- * water cell has non-positive total depth H + eta (the model has no drying). */
+#define SW2D_ORACLE_FRICTION 1
+#define SW2D_ORACLE_FILTER_UV 2
+
+/* active u face (east face of cell j,i) and active v face (north face) */
+static int u_face(const unsigned char *mask, int nx, int ny, int j, int i) {
+    return is_wet(mask, nx, ny, j, i) && is_wet(mask, nx, ny, j, i + 1);
+}
+static int v_face(const unsigned char *mask, int nx, int ny, int j, int i) {
+    return is_wet(mask, nx, ny, j, i) && is_wet(mask, nx, ny, j + 1, i);
+}
+
+/* Shapiro smoothing of face values a (active where act() says so) into out */
+static void filter_faces(int nx, int ny, double e4, const unsigned char *mask, const double *a, double *out,
+                         int (*act)(const unsigned char *, int, int, int, int)) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            double o = 0.0;
+            if (act(mask, nx, ny, j, i)) {
+                double c = AT(a, j, i);
+                double s = 0.0;
+                if (act(mask, nx, ny, j, i + 1)) s += AT(a, j, i + 1) - c;
+                if (act(mask, nx, ny, j, i - 1)) s += AT(a, j, i - 1) - c;
+                if (act(mask, nx, ny, j + 1, i)) s += AT(a, j + 1, i) - c;
+                if (act(mask, nx, ny, j - 1, i)) s += AT(a, j - 1, i) - c;
+                o = c + e4 * s;
+            }
+            AT(out, j, i) = o;
+        }
+    }
+}
+
+/* One step. scratch holds 3*nx*ny doubles (Fx, Fy, es). flags: SW2D_ORACLE_FRICTION
+ * (quadratic bottom friction with coefficient cd), SW2D_ORACLE_FILTER_UV. Returns 0, or 1
+ * if a water cell has non-positive total depth H + eta (the model has no drying). */
 int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, double eps,
                      const double *H, const unsigned char *mask,
                      const double *eta, const double *u, const double *v,
                      double *eta_out, double *u_out, double *v_out,
-                     double *scratch, int nthreads) {
+                     double *scratch, int nthreads, int flags, double cd) {
     const double cx = g * dt / dx, cy = g * dt / dy;
+    const double kf = dt * cd;
     const double rx = dt / dx, ry = dt / dy;
     const double e4 = eps / 4.0;
     double *Fx = scratch;
@@ -77,12 +119,20 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
             double us = 0.0, vs = 0.0, fx = 0.0, fy = 0.0;
             if (au) {
                 us = AT(u, j, i) - cx * (AT(eta, j, i + 1) - AT(eta, j, i));
+                if (flags & SW2D_ORACLE_FRICTION) {
+                    double hf = 0.5 * ((AT(H, j, i) + AT(eta, j, i)) + (AT(H, j, i + 1) + AT(eta, j, i + 1)));
+                    us = us / (1.0 + kf * fabs(AT(u, j, i)) / hf);
+                }
                 double h_up = us > 0.0 ? AT(H, j, i) + AT(eta, j, i)
                                        : AT(H, j, i + 1) + AT(eta, j, i + 1);
                 fx = us * h_up;
             }
             if (av) {
                 vs = AT(v, j, i) - cy * (AT(eta, j + 1, i) - AT(eta, j, i));
+                if (flags & SW2D_ORACLE_FRICTION) {
+                    double hf = 0.5 * ((AT(H, j, i) + AT(eta, j, i)) + (AT(H, j + 1, i) + AT(eta, j + 1, i)));
+                    vs = vs / (1.0 + kf * fabs(AT(v, j, i)) / hf);
+                }
                 double h_up = vs > 0.0 ? AT(H, j, i) + AT(eta, j, i)
                                        : AT(H, j + 1, i) + AT(eta, j + 1, i);
                 fy = vs * h_up;
@@ -124,6 +174,14 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
             }
             AT(eta_out, j, i) = out;
         }
+    }
+
+    /* variant: the velocity update filters the predicted velocities (Fx, Fy are free now) */
+    if (flags & SW2D_ORACLE_FILTER_UV) {
+        filter_faces(nx, ny, e4, mask, u_out, Fx, u_face);
+        filter_faces(nx, ny, e4, mask, v_out, Fy, v_face);
+        memcpy(u_out, Fx, sizeof(double) * (size_t)nx * ny);
+        memcpy(v_out, Fy, sizeof(double) * (size_t)nx * ny);
     }
     return dry;
 }
@@ -167,7 +225,8 @@ void sw2d_oracle_reduce(int nx, int ny, double dx, double dy, const double *H,
  * 2 if memory ran out. */
 int sw2d_oracle_run(int nx, int ny, double dx, double dy, double g, double dt, double eps,
                     const double *H, const unsigned char *mask,
-                    double *eta, double *u, double *v, int nsteps, double *red, int nthreads) {
+                    double *eta, double *u, double *v, int nsteps, double *red, int nthreads, int flags,
+                    double cd) {
     size_t n = (size_t)nx * ny;
     double *buf = (double *)malloc(sizeof(double) * (6 * n + 2 * (size_t)ny));
     if (!buf) return 2;
@@ -177,7 +236,7 @@ int sw2d_oracle_run(int nx, int ny, double dx, double dy, double g, double dt, d
     int rc = 0;
     for (int s = 0; s < nsteps && rc == 0; ++s) {
         rc = sw2d_oracle_step(nx, ny, dx, dy, g, dt, eps, H, mask, ce, cu, cv, ne, nu, nv,
-                              scratch, nthreads);
+                              scratch, nthreads, flags, cd);
         if (red) sw2d_oracle_reduce(nx, ny, dx, dy, H, mask, ne, nu, nv, red + 4 * (size_t)s, rowbuf);
         double *t;
         t = ce; ce = ne; ne = t;

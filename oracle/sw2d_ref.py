@@ -27,10 +27,10 @@ def _bind(path):
     lib = ctypes.CDLL(path)
     lib.sw2d_oracle_step.restype = ctypes.c_int
     lib.sw2d_oracle_step.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 5 + [
-        _dp, _u8p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        _dp, _u8p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
     lib.sw2d_oracle_run.restype = ctypes.c_int
     lib.sw2d_oracle_run.argtypes = [ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 5 + [
-        _dp, _u8p, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_int]
+        _dp, _u8p, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
     lib.sw2d_oracle_reduce.restype = None
     lib.sw2d_oracle_reduce.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double, _dp, _u8p, _dp, _dp, _dp, _dp, _dp]
@@ -79,16 +79,22 @@ class DryCellError(RuntimeError):
     """A water cell reached non-positive total depth (the model has no drying)."""
 
 
-def run(nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, nsteps, nthreads=1, reductions=True):
+FRICTION = 1   # quadratic bottom friction on the predictor (coefficient cd)
+FILTER_UV = 2  # the Shapiro filter on the predicted velocities as well
+
+
+def run(nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, nsteps, nthreads=1, reductions=True, flags=0, cd=0.0):
     """Advance ``nsteps`` steps in FP64. Returns (eta, u, v, red) with red[s] = (V_tot, V_disp,
-    max|u|, max|v|) after step s, or None when ``reductions`` is False."""
+    max|u|, max|v|) after step s, or None when ``reductions`` is False. ``flags`` selects the
+    model variants (FRICTION with coefficient ``cd``, FILTER_UV)."""
     lib = _load()
     H, mask = _f64(H), _u8(mask)
     eta, u, v = _f64(eta).copy(), _f64(u).copy(), _f64(v).copy()
     assert H.shape == mask.shape == eta.shape == u.shape == v.shape == (ny, nx)
     red = np.zeros((max(nsteps, 1), 4)) if reductions else None
     rc = lib.sw2d_oracle_run(nx, ny, dx, dy, g, dt, eps, _p(H), _p(mask, _u8p), _p(eta), _p(u),
-                             _p(v), int(nsteps), _p(red) if red is not None else None, int(nthreads))
+                             _p(v), int(nsteps), _p(red) if red is not None else None, int(nthreads),
+                             int(flags), float(cd))
     if rc == 1:
         raise DryCellError("a water cell dried out")
     if rc != 0:
@@ -96,11 +102,11 @@ def run(nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, nsteps, nthreads=1, redu
     return eta, u, v, (red[:nsteps] if red is not None else None)
 
 
-def run_case(case, nsteps=None, nthreads=1, reductions=True):
+def run_case(case, nsteps=None, nthreads=1, reductions=True, flags=0, cd=0.0):
     """``run`` on a ``Case``-like object with fields nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v."""
     n = case.steps if nsteps is None else nsteps
     return run(case.nx, case.ny, case.dx, case.dy, case.g, case.dt, case.eps, case.H, case.mask,
-               case.eta, case.u, case.v, n, nthreads=nthreads, reductions=reductions)
+               case.eta, case.u, case.v, n, nthreads=nthreads, reductions=reductions, flags=flags, cd=cd)
 
 
 def reduce(nx, ny, dx, dy, H, mask, eta, u, v):

@@ -30,6 +30,12 @@ MUTANTS = {
     "shapiro_eps_over_2": ("const double e4 = eps / 4.0;", "const double e4 = eps / 2.0;"),
     "depth_from_new_side": ("AT(H, j + 1, i) + AT(eta, j + 1, i);", "AT(H, j, i) + AT(eta, j + 1, i);"),
     "volume_counts_land": ("if (AT(mask, j, i)) {", "{"),
+    # model variants
+    "friction_uses_new_velocity": ("us = us / (1.0 + kf * fabs(AT(u, j, i)) / hf);", "us = us / (1.0 + kf * fabs(us) / hf);"),
+    "friction_one_sided_depth": ("double hf = 0.5 * ((AT(H, j, i) + AT(eta, j, i)) + (AT(H, j, i + 1) + AT(eta, j, i + 1)));",
+                                 "double hf = AT(H, j, i) + AT(eta, j, i);"),
+    "uv_filter_over_inactive_faces": ("if (act(mask, nx, ny, j + 1, i)) s += AT(a, j + 1, i) - c;", "s += AT(a, j + 1, i) - c;"),
+    "uv_filter_v_on_u_faces": ("filter_faces(nx, ny, e4, mask, v_out, Fy, v_face);", "filter_faces(nx, ny, e4, mask, v_out, Fy, u_face);"),
 }
 
 
@@ -68,7 +74,16 @@ def _pin_volume():
     test_volume_is_conserved_in_a_closed_basin()
 
 
-PINS = (_pin_golden, _pin_modes, _pin_exact, _pin_volume)
+def _pin_variants():
+    from tests import test_oracle_variants as tv
+    tv.test_friction_is_the_closed_form_on_a_level_surface()
+    tv.test_friction_divides_the_predictor_by_the_old_speed()
+    for k, l in ((1, 0), (2, 3)):
+        tv.test_velocity_filter_modes_decay_by_the_closed_form(k, l)
+    tv.test_velocity_filter_conserves_the_face_sum_and_follows_the_surface_update()
+
+
+PINS = (_pin_golden, _pin_modes, _pin_exact, _pin_volume, _pin_variants)
 
 
 def test_unmutated_oracle_passes_every_pin():
