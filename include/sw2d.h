@@ -52,13 +52,30 @@ enum {
     SW2D_ENOSPC = -5     /* workspace smaller than sw2d_workspace_bytes() */
 };
 
+/* Model variants (flags of sw2d_params; the paper's model has neither - they are the
+ * textbook family's options either side of it):
+ *  SW2D_FRICTION:  quadratic bottom friction on the predictor,
+ *                  us = (u - g dt/dx (eta_E - eta)) / (1 + dt cd |u| / h_face),
+ *                  h_face = mean total depth (H + eta) of the face's two cells, |u| and the
+ *                  depths of the old state; vs likewise.
+ *  SW2D_FILTER_UV: the velocity update applies the Shapiro filter to the predicted
+ *                  velocities as well: u' = us + eps/4 sum over active neighbouring u faces
+ *                  (east, west, north, south) of (us_nb - us); v' likewise. The surface update
+ *                  of the step uses the unfiltered us, vs.
+ * A handle with flags steps one step per pass (sw2d_set_time_blocking refuses K > 1), and
+ * the batched and unfused paths take flags = 0 only. */
+#define SW2D_FRICTION 1u
+#define SW2D_FILTER_UV 2u
+
 /* Grid and constants. nx, ny count every cell, land border included (>= 3 each).
- * dx, dy, dt > 0 and finite; g >= 0 and finite; eps in [0, 1] (Shapiro weight).
- * flags is reserved and must be 0. */
+ * dx, dy, dt > 0 and finite; g >= 0 and finite; eps in [0, 1] (Shapiro weight);
+ * flags: 0 or a combination of SW2D_FRICTION and SW2D_FILTER_UV; cd >= 0 and finite, the
+ * bottom-drag coefficient (used with SW2D_FRICTION, ignored otherwise). */
 typedef struct {
     int32_t nx, ny;
     double dx, dy, g, dt, eps;
     uint32_t flags;
+    double cd;
 } sw2d_params;
 
 /* The folds of the state after one step (32 bytes; the device writes this layout). */

@@ -63,7 +63,8 @@ bool params_ok(const sw2d_params* p) {
     if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dt)) return false;
     if (!std::isfinite(p->g) || p->g < 0.0) return false;
     if (!std::isfinite(p->eps) || p->eps < 0.0 || p->eps > 1.0) return false;
-    if (p->flags != 0) return false;
+    if (p->flags & ~(uint32_t)(SW2D_FRICTION | SW2D_FILTER_UV)) return false;
+    if (!std::isfinite(p->cd) || p->cd < 0.0) return false;
     return true;
 }
 
@@ -112,6 +113,7 @@ StepCoef make_coef(const sw2d_params* p) {
     k.rx = (float)(p->dt / p->dx);
     k.ry = (float)(p->dt / p->dy);
     k.e4 = (float)(p->eps / 4.0);
+    k.kf = (p->flags & SW2D_FRICTION) ? (float)(p->dt * p->cd) : 0.f;
     return k;
 }
 
@@ -153,7 +155,7 @@ int enqueue_steps(sw2d_ctx* h, int32_t nsteps, hipEvent_t* ev, double* total_ms)
             SW2D_HIP(launch_stepk(k, src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part, h->part_capacity,
                                   g, h->coef, h->stream));
         else
-            SW2D_HIP(launch_step(src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part, g, h->coef,
+            SW2D_HIP(launch_step((int)h->p.flags, src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part, g, h->coef,
                                  h->stream));
         if (ev) SW2D_HIP(hipEventRecord(ev[2 * passes + 1], h->stream));
         h->cur ^= 1;
@@ -290,6 +292,7 @@ size_t sw2d_unfused_scratch_bytes(const sw2d_params* p) {
 
 int sw2d_step_unfused(sw2d_t h, int32_t nsteps, float* d_scratch, size_t scratch_bytes) {
     if (!h || nsteps < 0 || !d_scratch) return SW2D_ESTATE;
+    if (h->p.flags != 0) return SW2D_EINVAL;  // the comparison path has no model variants
     if (scratch_bytes < sw2d_unfused_scratch_bytes(&h->p)) return SW2D_ENOSPC;
     const int nparts = h->part_capacity < 1024 ? h->part_capacity : 1024;
     int pending = 0;
@@ -320,6 +323,7 @@ int sw2d_set_band_rows(sw2d_t h, int32_t rows) {
 int sw2d_set_time_blocking(sw2d_t h, int32_t steps_per_pass, int32_t rows) {
     if (!h) return SW2D_ESTATE;
     if (steps_per_pass < 1 || steps_per_pass > kMaxStepsPerPass) return SW2D_EINVAL;
+    if (steps_per_pass >= 2 && h->p.flags != 0) return SW2D_EINVAL;  // variants step one at a time
     if (steps_per_pass >= 2) {
         if (rows < kMinRows || rows > h->p.ny) return SW2D_EINVAL;
         // the same band height for the shorter passes that finish a step count

@@ -370,7 +370,7 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
     L.tiles_of.resize(n);
     L.n_tiles = 0;
     for (int i = 0; i < n; ++i) {
-        if (!sw2d::detail::params_valid(&p[i])) return false;
+        if (!sw2d::detail::params_valid(&p[i]) || p[i].flags != 0) return false;  // plain model only
         const int rows = rows_for(p[i], band_rows, i);
         if (rows < 1 || (band_rows && band_rows[i] < kMinRows)) return false;
         L.hp[i] = off;

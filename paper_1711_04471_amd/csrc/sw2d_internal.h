@@ -46,7 +46,11 @@ struct StepCoef {
     float cx, cy;  // g dt / dx, g dt / dy
     float rx, ry;  // dt / dx, dt / dy
     float e4;      // eps / 4
+    float kf;      // dt cd (bottom friction; 0 without it)
 };
+
+// Model variants of the step (the flags of sw2d_params), as template arguments.
+enum : int { kVarFriction = 1, kVarFilterUV = 2, kVarAll = kVarFriction | kVarFilterUV };
 
 enum : uint32_t {
     kWetBorder = 1u,
@@ -75,7 +79,8 @@ inline StepGeometry make_geometry(int nx, int ny, int rows, int strip_out = kStr
     return g;
 }
 
-hipError_t launch_step(const float* eta, const float* u, const float* v, const float* hp,
+// kvar: the model variants (0 for the plain step).
+hipError_t launch_step(int kvar, const float* eta, const float* u, const float* v, const float* hp,
                        float* eta_o, float* u_o, float* v_o, FoldPartial* part,
                        const StepGeometry& geo, const StepCoef& k, hipStream_t s);
 // K = 2..4 steps in one pass (geometry from make_geometry(..., strip_out_for(K))); the

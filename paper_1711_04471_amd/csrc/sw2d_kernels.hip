@@ -105,6 +105,7 @@ __device__ __forceinline__ void workgroup_fold(double disp, float mu, float mv, 
     }
 }
 
+template <int kVar>
 __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
     const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
     const float* __restrict__ hp, float* __restrict__ eta_o, float* __restrict__ u_o,
@@ -139,12 +140,12 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
         // the same moment (both at their start or both at their end) and the second
         // read hits L2 instead of HBM.
         if (band & 1)
-            march<false>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1,
-                         k, f_disp, f_mu, f_mv);
+            march<false, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1,
+                               k, f_disp, f_mu, f_mv);
         else
 #endif
-            march<true>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1,
-                        k, f_disp, f_mu, f_mv);
+            march<true, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1,
+                              k, f_disp, f_mu, f_mv);
     }
     workgroup_fold(f_disp, f_mu, f_mv, part + blockIdx.x);
 }
@@ -301,11 +302,29 @@ __global__ __launch_bounds__(256) void sw2d_hsum_final_kernel(const double* __re
 // ---------------------------------------------------------------------------------------
 // Host-side launchers (called by the C ABI in sw2d_api.hip)
 
-hipError_t launch_step(const float* eta, const float* u, const float* v, const float* hp,
+hipError_t launch_step(int kvar, const float* eta, const float* u, const float* v, const float* hp,
                        float* eta_o, float* u_o, float* v_o, FoldPartial* part,
                        const StepGeometry& geo, const StepCoef& k, hipStream_t s) {
-    hipLaunchKernelGGL(sw2d_step_kernel, dim3(geo.nblocks), dim3(kGroupThreads), 0, s, eta, u, v, hp,
-                       eta_o, u_o, v_o, part, geo, k);
+    const dim3 grid(geo.nblocks), block(kGroupThreads);
+    switch (kvar) {
+        case 0:
+            hipLaunchKernelGGL(sw2d_step_kernel<0>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, geo, k);
+            break;
+        case kVarFriction:
+            hipLaunchKernelGGL(sw2d_step_kernel<kVarFriction>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o,
+                               part, geo, k);
+            break;
+        case kVarFilterUV:
+            hipLaunchKernelGGL(sw2d_step_kernel<kVarFilterUV>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o,
+                               part, geo, k);
+            break;
+        case kVarAll:
+            hipLaunchKernelGGL(sw2d_step_kernel<kVarAll>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part,
+                               geo, k);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

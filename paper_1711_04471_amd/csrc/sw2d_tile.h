@@ -63,11 +63,20 @@ __device__ __forceinline__ void store(float* p, float x) {
 // x-part of the surface update (pe = eta - dt/dx (Fx - Fx_W)).
 struct RowX {
     float e, h, pe, us;
-    bool w, wE, wW;
+    bool w, wE, wW, au;
 };
+
+// Quadratic bottom friction (variant): the predictor divided by 1 + dt cd |u_old| / h_face,
+// h_face the mean total depth of the face's two cells.
+__device__ __forceinline__ float friction(float pred, float u_old, float h_a, float h_b, const StepCoef& k) {
+#pragma clang fp contract(off)
+    const float hf = 0.5f * (h_a + h_b);
+    return pred / (1.f + k.kf * fabsf(u_old) / hf);
+}
 
 // Floating-point contraction is off in the step's arithmetic and every fused multiply-add
 // is written out, so each kernel that inlines these routines rounds alike, bit for bit.
+template <int kVar = 0>
 __device__ __forceinline__ RowX row_x(float e, float hpr, float ur, const StepCoef& k) {
 #pragma clang fp contract(off)
     RowX o;
@@ -80,7 +89,9 @@ __device__ __forceinline__ RowX row_x(float e, float hpr, float ur, const StepCo
     o.wE = hpE > 0.f;
     o.wW = hpW > 0.f;
     const bool au = o.w && o.wE;
+    o.au = au;
     o.us = au ? fmaf(-k.cx, eE - e, ur) : 0.f;
+    if constexpr ((kVar & kVarFriction) != 0) o.us = au ? friction(o.us, ur, o.h, hpE + eE, k) : 0.f;
     // an inactive face has us = 0, so its flux is 0 without a second select
     const float fx = o.us * (o.us > 0.f ? o.h : hpE + eE);
     const float fxW = from_west(fx);
@@ -89,11 +100,14 @@ __device__ __forceinline__ RowX row_x(float e, float hpr, float ur, const StepCo
 }
 
 // The y-face between a southern cell (lo) and its northern neighbour (hi).
+template <int kVar = 0>
 __device__ __forceinline__ void face_y(float v_lo, float e_lo, float h_lo, bool w_lo, float e_hi,
-                                       float h_hi, bool w_hi, const StepCoef& k, float& vs, float& fy) {
+                                       float h_hi, bool w_hi, const StepCoef& k, float& vs, float& fy,
+                                       bool& av) {
 #pragma clang fp contract(off)
-    const bool av = w_lo && w_hi;
+    av = w_lo && w_hi;
     vs = av ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
+    if constexpr ((kVar & kVarFriction) != 0) vs = av ? friction(vs, v_lo, h_lo, h_hi, k) : 0.f;
     fy = vs * (vs > 0.f ? h_lo : h_hi);  // vs = 0 on an inactive face
 }
 
@@ -111,13 +125,29 @@ __device__ __forceinline__ float shapiro(float es_c, bool w_c, bool wE, bool wW,
     return w_c ? fmaf(e4, s, es_c) : 0.f;
 }
 
+// The same filter on face velocities (variant): c on an active face, neighbours east and
+// west (lane exchange) and north and south, each counted only when active.
+__device__ __forceinline__ float shapiro_face(float c, bool act, float n_val, bool n_act, float s_val, bool s_act,
+                                              float e4) {
+#pragma clang fp contract(off)
+    const float cE = from_east(c), cW = from_west(c);
+    const float a = act ? 1.f : 0.f;
+    const bool actE = from_east(a) > 0.f, actW = from_west(a) > 0.f;
+    float s = actE ? cE - c : 0.f;
+    if (actW) s += cW - c;
+    if (n_act) s += n_val - c;
+    if (s_act) s += s_val - c;
+    return act ? fmaf(e4, s, c) : 0.f;
+}
+
 // One time step of one wave's strip as a row pipeline. push() consumes input row r (in
 // march order) and returns the new state of the row two behind it: row r gives the x-face
 // predictor, flux and partial surface update; row r-1 (r+1 marching south) its y-face and
 // the predicted surface es; row r-2 (r+2) the Shapiro filter. Every output value is the
 // same expression in either direction.
-template <bool kNorth>
+template <bool kNorth, int kVar = 0>
 struct Stage {
+    static constexpr bool kFilterUV = (kVar & kVarFilterUV) != 0;
     // rows 1, 2 and 3 behind the one being consumed (in march order)
     float e1 = 0.f, h1 = 0.f, hp1 = 0.f, v1 = 0.f, pe1 = 0.f, us1 = 0.f, fy1 = 0.f, vs1 = 0.f;
     bool w1 = false, wE1 = false, wW1 = false;
@@ -125,18 +155,33 @@ struct Stage {
     bool w2 = false, wE2 = false, wW2 = false;
     float es3 = 0.f;
     bool w3 = false;
+    // velocity-filter variant: face activity travelling with the face values, one more row
+    bool au1 = false, au2 = false, au3 = false, av1 = false, av2 = false, av3 = false;
+    float us3 = 0.f, vs3 = 0.f;
 
     __device__ __forceinline__ void push(float e, float hpr, float ur, float vr, const StepCoef& k,
                                          float& eta_o, float& u_o, float& v_o, float& hp_o) {
-        const RowX X = row_x(e, hpr, ur, k);
+        const RowX X = row_x<kVar>(e, hpr, ur, k);
         if constexpr (kNorth) {
             // y-face between rows r-1 and r, then es of row r-1, then the output row r-2
             float vs, fy;
-            face_y(v1, e1, h1, w1, X.e, X.h, X.w, k, vs, fy);
+            bool av;
+            face_y<kVar>(v1, e1, h1, w1, X.e, X.h, X.w, k, vs, fy, av);
             const float es = w1 ? fmaf(-k.ry, fy - fy2, pe1) : 0.f;
             eta_o = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
-            u_o = us2;
-            v_o = vs2;
+            if constexpr (kFilterUV) {
+                // north neighbour: row r-1 (u) and the face r-1|r (v); south: row r-3, face r-3|r-2
+                u_o = shapiro_face(us2, au2, us1, au1, us3, au3, k.e4);
+                v_o = shapiro_face(vs2, av2, vs, av, vs3, av3, k.e4);
+                us3 = us2;
+                au3 = au2;
+                vs3 = vs2;
+                av3 = av2;
+                av2 = av;
+            } else {
+                u_o = us2;
+                v_o = vs2;
+            }
             hp_o = hp2;
             es3 = es2;
             w3 = w2;
@@ -147,11 +192,24 @@ struct Stage {
         } else {
             // y-face between rows r and r+1, then es of row r+1, then the output row r+2
             float vs, fy;
-            face_y(vr, X.e, X.h, X.w, e1, h1, w1, k, vs, fy);
+            bool av;
+            face_y<kVar>(vr, X.e, X.h, X.w, e1, h1, w1, k, vs, fy, av);
             const float es = w1 ? fmaf(-k.ry, fy1 - fy, pe1) : 0.f;
             eta_o = shapiro(es2, w2, wE2, wW2, es3, w3, es, w1, k.e4);
-            u_o = us2;
-            v_o = vs2;
+            if constexpr (kFilterUV) {
+                // north neighbour: row r+3 (u) and the face r+3|r+4 (v); south: row r+1, face r+1|r+2
+                u_o = shapiro_face(us2, au2, us3, au3, us1, au1, k.e4);
+                v_o = shapiro_face(vs2, av2, vs3, av3, vs1, av1, k.e4);
+                us3 = us2;
+                au3 = au2;
+                vs3 = vs2;
+                av3 = av2;
+                av2 = av1;
+                av1 = av;
+            } else {
+                u_o = us2;
+                v_o = vs2;
+            }
             hp_o = hp2;
             es3 = es2;
             w3 = w2;
@@ -159,6 +217,10 @@ struct Stage {
             vs2 = vs1;
             fy1 = fy;
             vs1 = vs;
+        }
+        if constexpr (kFilterUV) {
+            au2 = au1;
+            au1 = X.au;
         }
         us2 = us1;
         hp2 = hp1;
@@ -299,7 +361,7 @@ struct LaneFolds {
 
 // One wave marches a band [j0, j1) of its strip, north (kNorth) or south, and writes the
 // new state of its output lanes.
-template <bool kNorth>
+template <bool kNorth, int kVar = 0>
 __device__ __forceinline__ void march(const float* __restrict__ eta, const float* __restrict__ u,
                                       const float* __restrict__ v, const float* __restrict__ hp,
                                       float* __restrict__ eta_o, float* __restrict__ u_o,
@@ -312,7 +374,7 @@ __device__ __forceinline__ void march(const float* __restrict__ eta, const float
     RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
     const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, step, n_rows);
-    Stage<kNorth> A;
+    Stage<kNorth, kVar> A;
     LaneFolds F;
     for (int i = 0; i < n_rows; ++i) {
         const int r = r_first + i * step;

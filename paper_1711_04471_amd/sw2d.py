@@ -15,9 +15,13 @@ RED_DTYPE = np.dtype([("step", np.int64), ("vol_total", np.float64), ("vol_disp"
                       ("max_abs_u", np.float32), ("max_abs_v", np.float32)])
 
 
-def params(nx, ny, dx, dy, g, dt, eps, flags=0) -> sw2d_params:
+FRICTION = 1   # quadratic bottom friction on the predictor (coefficient cd)
+FILTER_UV = 2  # the Shapiro filter on the predicted velocities as well
+
+
+def params(nx, ny, dx, dy, g, dt, eps, flags=0, cd=0.0) -> sw2d_params:
     return sw2d_params(int(nx), int(ny), float(dx), float(dy), float(g), float(dt), float(eps),
-                       int(flags))
+                       int(flags), float(cd))
 
 
 def workspace_bytes(p: sw2d_params) -> int:
@@ -43,13 +47,13 @@ class Sw2d:
     shape [ny][nx]). Device buffers are torch tensors owned by this object.
     """
 
-    def __init__(self, nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, device="cuda"):
+    def __init__(self, nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, device="cuda", flags=0, cd=0.0):
         lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("Sw2d runs on a GPU device only")
         self.nx, self.ny = int(nx), int(ny)
-        self.p = params(nx, ny, dx, dy, g, dt, eps)
+        self.p = params(nx, ny, dx, dy, g, dt, eps, flags, cd)
         n = self.nx * self.ny
         self.H = _dev_tensor(H, torch.float32, self.device)
         self.mask = _dev_tensor(mask, torch.uint8, self.device)
@@ -68,9 +72,9 @@ class Sw2d:
         self.h = h
 
     @classmethod
-    def from_case(cls, case, device="cuda"):
+    def from_case(cls, case, device="cuda", flags=0, cd=0.0):
         return cls(case.nx, case.ny, case.dx, case.dy, case.g, case.dt, case.eps, case.H,
-                   case.mask, case.eta, case.u, case.v, device=device)
+                   case.mask, case.eta, case.u, case.v, device=device, flags=flags, cd=cd)
 
     def _handle(self):
         if self.h is None:

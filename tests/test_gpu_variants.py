@@ -1,0 +1,85 @@
+"""GPU parity of the model variants (bottom friction, Shapiro filter on the velocities)
+against the FP64 oracle with the same flags.
+
+Bar as for the plain step: eta, u, v within 1e-5 relative L2, land and inactive faces
+exactly 0, folds within 1e-5; bitwise independence of the band height (which also swaps
+the march direction of half the bands); a lake at rest stays bitwise at rest. Each case
+also checks that the variant moves the result far beyond the tolerance, so the parity is
+not that of the plain step.
+"""
+import numpy as np
+import pytest
+
+from oracle import sw2d_ref
+from paper_1711_04471_amd import inputs
+from paper_1711_04471_amd.sw2d import FILTER_UV, FRICTION, Sw2d
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+CD = 0.5  # a strong drag, so its arithmetic shows clearly within the test's steps
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _gpu(case, flags, n, band_rows=None):
+    with Sw2d.from_case(case, flags=flags, cd=CD) as sim:
+        if band_rows is not None:
+            sim.band_rows = band_rows
+        sim.step(n)
+        red = sim.reduce(n)
+        e, u, v = sim.state_numpy()
+    return e, u, v, red
+
+
+@pytest.mark.parametrize("flags", [FRICTION, FILTER_UV, FRICTION | FILTER_UV])
+@pytest.mark.parametrize("shape", [(66, 66), (130, 257), (301, 97)])
+def test_variant_matches_oracle(shape, flags):
+    nx, ny = shape
+    c = inputs.small_basin(nx, ny, seed=nx + 5 * ny, steps=80) if shape != (66, 66) else inputs.gaussian_basin_64()
+    n = 80
+    _say(f"variant {flags} on {c.name} {nx}x{ny}")
+    e, u, v, red = _gpu(c, flags, n)
+    oe, ou, ov, ored = sw2d_ref.run_case(c, nsteps=n, flags=flags, cd=CD)
+    errs = (rel_l2(e, oe), rel_l2(u, ou), rel_l2(v, ov))
+    assert max(errs) <= TOL, errs
+    wet = c.mask != 0
+    au = np.zeros_like(wet)
+    au[:, :-1] = wet[:, :-1] & wet[:, 1:]
+    av = np.zeros_like(wet)
+    av[:-1] = wet[:-1] & wet[1:]
+    assert not e[~wet].any() and not u[~au].any() and not v[~av].any()
+    for col, k in (("vol_total", 0), ("vol_disp", 1), ("max_abs_u", 2), ("max_abs_v", 3)):
+        np.testing.assert_allclose(red[col], ored[:, k], rtol=TOL, atol=1e-6 * c.dx * c.dy, err_msg=col)
+    pe, pu, pv, _ = sw2d_ref.run_case(c, nsteps=n)
+    assert max(rel_l2(u, pu), rel_l2(v, pv)) > 100 * TOL  # the variant changed the answer
+
+
+@pytest.mark.parametrize("flags", [FRICTION | FILTER_UV, FILTER_UV])
+def test_variant_is_band_height_independent(flags):
+    c = inputs.small_basin(200, 173, seed=21, steps=50)
+    runs = [_gpu(c, flags, 50, band_rows=r) for r in (8, 16, 40)]
+    for other in runs[1:]:
+        for a, b in zip(runs[0][:3], other[:3]):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("flags", [FRICTION, FILTER_UV, FRICTION | FILTER_UV])
+def test_variant_keeps_lake_at_rest(flags):
+    c = inputs.lake_at_rest(150, 90, seed=3)
+    e, u, v, _ = _gpu(c, flags, 40)
+    assert np.array_equal(e, c.eta) and not u.any() and not v.any()
+
+
+def test_variant_handles_refuse_multi_step_passes():
+    from paper_1711_04471_amd._lib import Sw2dError
+    c = inputs.small_basin(64, 64, seed=2, steps=5)
+    with Sw2d.from_case(c, flags=FILTER_UV, cd=0.0) as sim:
+        with pytest.raises(Sw2dError):
+            sim.set_time_blocking(3, rows=32)
+        sim.step(2)
+        with pytest.raises(Sw2dError):
+            sim.step_unfused(1)
