@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--surrogate-fine", type=int, default=4096)
     ap.add_argument("--surrogate-tests", type=int, default=3)
     ap.add_argument("--damping", type=float, default=0.5)
+    ap.add_argument("--no-variants", action="store_true", help="skip the model-variant leg")
     ap.add_argument("--no-sor", action="store_true", help="skip the SOR pressure-solver leg")
     ap.add_argument("--only-sor", action="store_true")
     ap.add_argument("--sor-solves", type=int, default=10)
@@ -271,6 +272,29 @@ def surrogate_leg(args, log):
     }
 
 
+def variants_leg(case, steps, log):
+    """The single-step kernel with each model variant (bottom friction, velocity filter,
+    both) on the same basin: same 28 B per cell-step, more arithmetic per cell."""
+    import torch
+
+    from paper_1711_04471_amd.sw2d import FILTER_UV, FRICTION, Sw2d
+
+    out = {}
+    cells = case.nx * case.ny
+    for name, flags in (("plain", 0), ("friction", FRICTION), ("filter_uv", FILTER_UV),
+                        ("friction+filter_uv", FRICTION | FILTER_UV)):
+        with Sw2d.from_case(case, flags=flags, cd=0.0025) as sim:
+            sim.band_rows = 16
+            sim.step(10)
+            torch.cuda.synchronize()
+            ms = sim.step_timed(steps)
+        gbs = cells * BYTES_PER_CELL_STEP / (ms * 1e-3) / 1e9
+        out[name] = {"ms_per_step": round(ms, 5), "value": round(cells / ms / 1e3, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"variants: {out}")
+    return {"workload": f"{case.name}, one step per pass, cd=0.0025", "unit": "Mcell-steps/s", **out}
+
+
 SOR_BYTES_PER_CELL_ITER = 16  # read the other colour, own colour and own f; write own colour
 
 
@@ -417,6 +441,8 @@ def main():
                             "max_abs_v": float(red["max_abs_v"][-1])},
     }
     sim.close()
+    if not args.no_variants:
+        out["variants"] = variants_leg(case, min(args.steps, 200), log)
     if not args.no_batched:
         out["batched"] = batched_leg(args.batched_steps, args.warmup, log)
     if not args.no_surrogate:
