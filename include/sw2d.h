@@ -231,6 +231,15 @@ int sw2d_batch_create(int32_t n, const sw2d_params *p, const float *const *d_H,
  * grid barrier always has every workgroup resident). Drops any recorded graph. */
 int sw2d_batch_set_launch(sw2d_batch_t b, int32_t steps_per_launch, int32_t use_graph, int32_t grid);
 
+/* Steps per pass of the batched kernel (temporal blocking as sw2d_set_time_blocking): 1
+ * (default), 2 or 3. Each member's strips then own 64 - 4K columns and its bands read a
+ * 2K-row halo; the grid meets once per pass; the states equal single steps bit for bit and
+ * the folds of every step are kept. Afterwards sw2d_batch_step takes multiples of K only.
+ * Synchronises the stream, rebuilds the tile list, drops a recorded graph, and lowers the
+ * grid to what the K-step kernel keeps resident. SW2D_EINVAL for K outside 1..3. */
+int sw2d_batch_set_time_blocking(sw2d_batch_t b, int32_t steps_per_pass);
+int32_t sw2d_batch_time_blocking(sw2d_batch_t b);
+
 /* Enqueue nsteps steps of every instance on the stream (no host synchronisation). With
  * graphs on, the first call for a given nsteps records the graph; later calls with the
  * same nsteps replay it. */

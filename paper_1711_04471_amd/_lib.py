@@ -59,6 +59,8 @@ SIGNATURES = {
     "sw2d_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int64]),
     "sw2d_set_band_rows": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "sw2d_band_rows": (ctypes.c_int32, [_vp]),
+    "sw2d_batch_set_time_blocking": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "sw2d_batch_time_blocking": (ctypes.c_int32, [_vp]),
     "sw2d_sor_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(sw2d_sor_params), ctypes.c_int32]),
     "sw2d_sor_run": (ctypes.c_int, [ctypes.POINTER(sw2d_sor_params), _vp, _vp, ctypes.c_int32, _vp, _vp,
                                     ctypes.c_size_t, _vp]),

@@ -18,6 +18,8 @@ import torch
 
 CLASSES = ((128, 256), (256, 512), (512, 1025))
 CANDIDATES = (8, 16, 32, 64)
+# with several steps per pass the band halo grows by 2 rows per step, so taller bands pay
+CANDIDATES_BY_K = {1: CANDIDATES, 2: (16, 32, 48, 64), 3: (16, 32, 48, 64, 96)}
 
 
 def size_class(nx: int):
@@ -41,9 +43,14 @@ def _arch(device) -> str:
     return getattr(props, "gcnArchName", props.name)
 
 
-def tune(cases, candidates=CANDIDATES, cache_path=None, steps=20, warmup=5, device="cuda",
-         default_rows=16, log=None):
-    """Band height per instance (list of ints), tuned per size class."""
+def tune(cases, candidates=None, cache_path=None, steps=24, warmup=6, device="cuda",
+         default_rows=16, log=None, steps_per_pass=1, whole=False):
+    """Band height per instance (list of ints), tuned per size class for the batched kernel
+    at ``steps_per_pass`` steps per pass (steps and warmup must be multiples of it). With
+    ``whole``, the tuned assignment is then timed against each uniform height on the whole
+    batch and the fastest kept."""
+    if candidates is None:
+        candidates = CANDIDATES_BY_K[steps_per_pass]
     from .sw2d import Sw2dBatch
     dev = torch.device(device)
     cache = {}
@@ -58,12 +65,13 @@ def tune(cases, candidates=CANDIDATES, cache_path=None, steps=20, warmup=5, devi
     for cls, idx in by_class.items():
         if cls is None:
             continue
-        key = f"{arch}|{cls[0]}-{cls[1]}|{','.join(map(str, candidates))}"
+        key = f"{arch}|K{steps_per_pass}|{cls[0]}-{cls[1]}|{','.join(map(str, candidates))}"
         if key not in cache:
             sub = [cases[i] for i in idx]
             timing, digests = {}, {}
             for cand in candidates:
                 with Sw2dBatch(sub, band_rows=[cand] * len(sub), device=dev) as b:
+                    b.set_time_blocking(steps_per_pass)
                     b.step(warmup)
                     timing[cand] = b.step_timed(steps)
                     digests[cand] = _digest(b)
@@ -76,6 +84,29 @@ def tune(cases, candidates=CANDIDATES, cache_path=None, steps=20, warmup=5, devi
                 log(f"autotune {cls}: {cache[key]}")
         for i in idx:
             rows[i] = int(cache[key]["rows"])
+    if whole and len(by_class) > 1:
+        # the classes share one grid, so the best heights class by class need not be the best
+        # together: time the tuned assignment against each uniform height on the whole batch
+        key = f"{arch}|K{steps_per_pass}|whole|{len(cases)}|{','.join(map(str, candidates))}|" \
+              f"{hashlib.sha1(json.dumps(rows).encode()).hexdigest()[:12]}"
+        if key not in cache:
+            options = {"tuned": rows}
+            options.update({str(c): [c] * len(cases) for c in candidates})
+            timing, digests = {}, {}
+            for name, opt in options.items():
+                with Sw2dBatch(cases, band_rows=[min(r, int(c.ny)) for r, c in zip(opt, cases)], device=dev) as b:
+                    b.set_time_blocking(steps_per_pass)
+                    b.step(warmup)
+                    timing[name] = b.step_timed(steps)
+                    digests[name] = _digest(b)
+            if len(set(digests.values())) != 1:
+                raise RuntimeError("parity guard: band-height assignments disagree on the whole batch")
+            best = min(timing, key=timing.get)
+            cache[key] = {"choice": best, "rows": [int(r) for r in options[best]],
+                          "ms_per_step": timing}
+            if log:
+                log(f"autotune whole batch: {best} {timing}")
+        rows = [int(r) for r in cache[key]["rows"]]
     if cache_path:
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:

@@ -63,22 +63,24 @@ constexpr int kLdsTiles = 64;  // descriptors a workgroup keeps in LDS at a time
 constexpr int kFlagStride = 16;  // 64-bit words between flags: one 128 B line each
 
 struct BatchControl {
-    unsigned error;        // 1: a barrier wait ran past its deadline
+    unsigned error;         // 1: a barrier wait ran past its deadline
     unsigned pad0;
-    long long steps_done;  // advanced by the kernel at the end of every launch
-    long long pad1[kFlagStride - 2];
+    long long steps_done;   // advanced by the kernel at the end of every launch
+    long long passes_done;  // passes over the state so far: its parity picks the current buffer
+    long long pad1[kFlagStride - 3];
     unsigned long long go;  // last epoch every workgroup has reached (own line)
     unsigned long long pad2[kFlagStride - 1];
     // followed by one flag line per workgroup
 };
 
 constexpr int kBatchThreads = kGroupThreads;
+constexpr int kMaxBatchK = 3;  // steps per pass of the batched kernel: 1..3
 constexpr int kBatchRing = 64;  // steps of per-instance folds kept
 
 struct BatchArgs {
     const BatchInst* inst;
     const BatchTile* tiles;
-    FoldPartial* part;  // [2][n_tiles]
+    FoldPartial* part;  // [2][K][n_tiles]
     sw2d_red* ring;     // [kBatchRing][n_inst]
     BatchControl* ctl;
     unsigned long long* flags;  // [grid][kFlagStride]
@@ -169,6 +171,12 @@ __device__ __forceinline__ void fold_step(const BatchArgs& a, int logical_wg, in
     for (int i = logical_wg; i < a.n_inst; i += nwg) fold_instance(a, i, slot, step);
 }
 
+// the K steps of one pass: partial slots slot0 .. slot0 + K - 1, steps first .. first + K - 1
+__device__ __forceinline__ void fold_pass(const BatchArgs& a, int logical_wg, int nwg, int slot0,
+                                          long long first, int K) {
+    for (int s = 0; s < K; ++s) fold_step(a, logical_wg, nwg, slot0 + s, first + s);
+}
+
 __device__ __forceinline__ int logical_block(int b, int n) {
     const int q = n / kXcds, r = n % kXcds;
     const int x = b % kXcds, k = b / kXcds;
@@ -198,14 +206,21 @@ __device__ __forceinline__ float uniform_f(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
+// K steps per pass over each member (temporal blocking as in the single-grid K-step
+// kernel: strips own 64 - 4K columns, bands read a 2K-row halo); the grid meets once per pass.
+template <int K>
 __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) {
     __shared__ BatchTile s_tiles[kLdsTiles];
     __shared__ double s_disp[kWavesPerGroup];
     __shared__ float s_mu[kWavesPerGroup], s_mv[kWavesPerGroup];
+    constexpr int kOut = (K == 1) ? kStripOut : kWave - 4 * K;
+    constexpr int kEdge = (K == 1) ? kHalo : 2 * K;
     const int nwg = gridDim.x;
     const int lwg = logical_block(blockIdx.x, nwg);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const long long base = a.ctl->steps_done;
+    const long long pbase = a.ctl->passes_done;
+    const int passes = a.steps / K;
     // this workgroup's tiles are lwg, lwg + nwg, ...
     const int my_tiles = lwg < a.n_tiles ? (a.n_tiles - lwg + nwg - 1) / nwg : 0;
     auto stage = [&](int k0) {  // descriptors k0 .. k0 + kLdsTiles - 1 of this workgroup
@@ -221,11 +236,11 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
     const bool resident = my_tiles <= kLdsTiles;
     if (resident) stage(0);
 
-    for (int s = 0; s < a.steps; ++s) {
-        const long long step_idx = base + s;  // 0-based index of the step being made
-        const int cur = (int)(step_idx & 1);
-        if (s > 0) fold_step(a, lwg, nwg, (s - 1) & 1, step_idx);
-        FoldPartial* part = a.part + (size_t)(s & 1) * a.n_tiles;
+    for (int ps = 0; ps < passes; ++ps) {
+        const long long step0 = base + (long long)ps * K;  // steps made before this pass
+        const int cur = (int)((pbase + ps) & 1);
+        if (ps > 0) fold_pass(a, lwg, nwg, ((ps - 1) & 1) * K, step0 - K + 1, K);
+        FoldPartial* part = a.part + (size_t)(ps & 1) * K * a.n_tiles;
         for (int k = 0; k < my_tiles; ++k) {
             const int kl = k % kLdsTiles;
             if (!resident && kl == 0) {
@@ -236,11 +251,10 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
             const int nx = uniform(t.nx), ny = uniform(t.ny);
             const int group2 = uniform(t.group2);
             const int strip = (group2 >> 1) * kWavesPerGroup + wave;
-            const int c = strip * kStripOut - kHalo + lane;
+            const int c = strip * kOut - kEdge + lane;
             const bool col_in = c >= 0 && c < nx;
-            const bool out_lane = col_in && lane >= kHalo && lane < kWave - kHalo;
-            double f_disp = 0.0;
-            float f_mu = 0.f, f_mv = 0.f;
+            const bool out_lane = col_in && lane >= kEdge && lane < kWave - kEdge;
+            LaneFolds F[K];
             if (strip < uniform(t.strips)) {
                 StepCoef kc;
                 kc.cx = uniform_f(t.k.cx);
@@ -248,6 +262,7 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
                 kc.rx = uniform_f(t.k.rx);
                 kc.ry = uniform_f(t.k.ry);
                 kc.e4 = uniform_f(t.k.e4);
+                kc.kf = 0.f;
                 const float* hp = uniform_ptr(t.hp);
                 const float* e0 = uniform_ptr(t.state[cur][0]);
                 const float* u0 = uniform_ptr(t.state[cur][1]);
@@ -256,40 +271,61 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
                 float* u1 = uniform_ptr(t.state[cur ^ 1][1]);
                 float* v1 = uniform_ptr(t.state[cur ^ 1][2]);
                 const int j0 = uniform(t.j0), j1 = uniform(t.j1);
-                if (group2 & 1)
-                    march<false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, f_disp, f_mu,
-                                 f_mv);
-                else
-                    march<true>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, f_disp, f_mu,
-                                f_mv);
-            }
-            batch_wave_sums(f_disp, f_mu, f_mv);
-            if (lane == 0) {
-                s_disp[wave] = f_disp;
-                s_mu[wave] = f_mu;
-                s_mv[wave] = f_mv;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double d = 0.0;
-                float m1 = 0.f, m2 = 0.f;
-#pragma unroll
-                for (int w = 0; w < kWavesPerGroup; ++w) {
-                    d += s_disp[w];
-                    m1 = fmaxf(m1, s_mu[w]);
-                    m2 = fmaxf(m2, s_mv[w]);
+                if constexpr (K == 1) {
+                    double f_disp = 0.0;
+                    float f_mu = 0.f, f_mv = 0.f;
+                    if (group2 & 1)
+                        march<false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, f_disp,
+                                     f_mu, f_mv);
+                    else
+                        march<true>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, f_disp,
+                                    f_mu, f_mv);
+                    F[0].disp = f_disp;
+                    F[0].mu_bits = __float_as_uint(f_mu);
+                    F[0].mv_bits = __float_as_uint(f_mv);
+                } else {
+                    if (group2 & 1)
+                        marchK<K, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, F);
+                    else
+                        marchK<K, true>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, F);
                 }
-                const int it = lwg + k * nwg;
-                part[it].disp = d;
-                part[it].mu = m1;
-                part[it].mv = m2;
             }
-            __syncthreads();
+            const int it = lwg + k * nwg;
+#pragma unroll
+            for (int s = 0; s < K; ++s) {
+                double f_disp = F[s].disp;
+                float f_mu = F[s].mu(), f_mv = F[s].mv();
+                batch_wave_sums(f_disp, f_mu, f_mv);
+                if (lane == 0) {
+                    s_disp[wave] = f_disp;
+                    s_mu[wave] = f_mu;
+                    s_mv[wave] = f_mv;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double d = 0.0;
+                    float m1 = 0.f, m2 = 0.f;
+#pragma unroll
+                    for (int w = 0; w < kWavesPerGroup; ++w) {
+                        d += s_disp[w];
+                        m1 = fmaxf(m1, s_mu[w]);
+                        m2 = fmaxf(m2, s_mv[w]);
+                    }
+                    FoldPartial* q = part + (size_t)s * a.n_tiles + it;
+                    q->disp = d;
+                    q->mu = m1;
+                    q->mv = m2;
+                }
+                __syncthreads();
+            }
         }
-        if (!grid_barrier(a, (unsigned long long)(step_idx + 1))) return;
+        if (!grid_barrier(a, (unsigned long long)(step0 + K))) return;
     }
-    fold_step(a, lwg, nwg, (a.steps - 1) & 1, base + a.steps);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->steps_done = base + a.steps;
+    fold_pass(a, lwg, nwg, ((passes - 1) & 1) * K, base + (long long)(passes - 1) * K + 1, K);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctl->steps_done = base + a.steps;
+        a.ctl->passes_done = pbase + passes;
+    }
 }
 
 }  // namespace sw2d
@@ -315,8 +351,13 @@ struct sw2d_bctx {
     int n_tiles;
     int grid;
     int steps_per_launch;
+    int steps_per_pass;            // K of the batched kernel, 1..kMaxBatchK
     bool use_graph;
     int64_t steps_done;
+    int64_t passes_done;
+    std::vector<BatchInst> inst;   // host copy (tile ranges for the current K)
+    std::vector<int> rows;         // band height per member
+    size_t tile_capacity;          // descriptors the workspace holds
     hipGraph_t graph;
     hipGraphExec_t exec;
     int graph_n;
@@ -357,6 +398,8 @@ constexpr int kMaxBatchGrid = 256 * 8;  // flag lines reserved: 8 workgroups on 
 // its deadline. 6 keeps a margin below that bound.
 constexpr int kBatchWgPerCu = 6;
 
+int batch_strip_out(int K) { return K == 1 ? kStripOut : kWave - 4 * K; }
+
 int rows_for(const sw2d_params& p, const int32_t* band_rows, int i) {
     int r = band_rows ? band_rows[i] : 16;
     if (r > p.ny) r = p.ny;
@@ -375,7 +418,8 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
         if (rows < 1 || (band_rows && band_rows[i] < kMinRows)) return false;
         L.hp[i] = off;
         off = align_up(off + (size_t)p[i].nx * p[i].ny * sizeof(float));
-        const int strips = (p[i].nx + kStripOut - 1) / kStripOut;
+        // the narrowest strips (most tiles) are those of the largest K
+        const int strips = (p[i].nx + batch_strip_out(kMaxBatchK) - 1) / batch_strip_out(kMaxBatchK);
         const int groups = (strips + kWavesPerGroup - 1) / kWavesPerGroup;
         const int bands = (p[i].ny + rows - 1) / rows;
         L.tiles_of[i] = groups * bands;
@@ -391,7 +435,7 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
     L.tiles = off;
     off = align_up(off + (size_t)L.n_tiles * sizeof(BatchTile));
     L.part = off;
-    off = align_up(off + 2 * (size_t)L.n_tiles * sizeof(FoldPartial));
+    off = align_up(off + 2 * (size_t)kMaxBatchK * L.n_tiles * sizeof(FoldPartial));
     L.ring = off;
     off = align_up(off + (size_t)kBatchRing * n * sizeof(sw2d_red));
     L.ctl = off;
@@ -413,12 +457,84 @@ int enqueue_chunks(sw2d_bctx* b, int32_t nsteps, hipStream_t s) {
     a.n_inst = b->n;
     a.n_tiles = b->n_tiles;
     a.timeout_ticks = b->timeout_ticks;
+    const int K = b->steps_per_pass;
+    const int per_launch = b->steps_per_launch >= K ? b->steps_per_launch / K * K : K;
     for (int32_t done = 0; done < nsteps;) {
-        a.steps = (nsteps - done < b->steps_per_launch) ? nsteps - done : b->steps_per_launch;
-        hipLaunchKernelGGL(sw2d_batch_kernel, dim3(b->grid), dim3(kBatchThreads), 0, s, a);
+        a.steps = (nsteps - done < per_launch) ? nsteps - done : per_launch;  // a multiple of K
+        switch (K) {
+            case 1:
+                hipLaunchKernelGGL(sw2d_batch_kernel<1>, dim3(b->grid), dim3(kBatchThreads), 0, s, a);
+                break;
+            case 2:
+                hipLaunchKernelGGL(sw2d_batch_kernel<2>, dim3(b->grid), dim3(kBatchThreads), 0, s, a);
+                break;
+            case 3:
+                hipLaunchKernelGGL(sw2d_batch_kernel<3>, dim3(b->grid), dim3(kBatchThreads), 0, s, a);
+                break;
+            default:
+                return SW2D_EINVAL;
+        }
         SW2D_BHIP(hipGetLastError());
         done += a.steps;
     }
+    return SW2D_OK;
+}
+
+// Tile list of every member for K steps per pass (strips of batch_strip_out(K) columns),
+// written to the device with the members' tile ranges.
+int upload_tiles(sw2d_bctx* b, int K) {
+    std::vector<BatchTile> tiles;
+    const int out = batch_strip_out(K);
+    for (int i = 0; i < b->n; ++i) {
+        BatchInst& in = b->inst[i];
+        in.strips = (in.nx + out - 1) / out;
+        in.tile_begin = (int)tiles.size();
+        const int rows = b->rows[i];
+        const int groups = (in.strips + kWavesPerGroup - 1) / kWavesPerGroup;
+        const int bands = (in.ny + rows - 1) / rows;
+        for (int blk = 0; blk < bands; blk += 2)
+            for (int gr = 0; gr < groups; ++gr)
+                for (int bd = blk; bd < blk + 2 && bd < bands; ++bd) {
+                    BatchTile t;
+                    std::memset(&t, 0, sizeof t);
+                    t.hp = in.hp;
+                    for (int buf = 0; buf < 2; ++buf)
+                        for (int f = 0; f < 3; ++f) t.state[buf][f] = in.state[buf][f];
+                    t.nx = in.nx;
+                    t.ny = in.ny;
+                    t.strips = in.strips;
+                    t.j0 = bd * rows;
+                    t.j1 = (t.j0 + rows < in.ny) ? t.j0 + rows : in.ny;
+                    t.group2 = 2 * gr + (bd & 1);
+                    t.inst = i;
+                    t.k = in.k;
+                    tiles.push_back(t);
+                }
+        in.tile_end = (int)tiles.size();
+    }
+    if (tiles.size() > b->tile_capacity) return SW2D_ENOSPC;
+    b->n_tiles = (int)tiles.size();
+    SW2D_BHIP(hipMemcpyAsync(b->d_inst, b->inst.data(), b->n * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
+    SW2D_BHIP(hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                             b->stream));
+    SW2D_BHIP(hipStreamSynchronize(b->stream));
+    return SW2D_OK;
+}
+
+// Workgroups of the K-step kernel the device holds at once (capped, see kBatchWgPerCu).
+int resident_grid(int K, int* out) {
+    int dev = 0, cus = 0, per_cu = 0;
+    SW2D_BHIP(hipGetDevice(&dev));
+    SW2D_BHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const void* fn = K == 1   ? reinterpret_cast<const void*>(&sw2d_batch_kernel<1>)
+                     : K == 2 ? reinterpret_cast<const void*>(&sw2d_batch_kernel<2>)
+                              : reinterpret_cast<const void*>(&sw2d_batch_kernel<3>);
+    SW2D_BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchThreads, 0));
+    if (per_cu < 1 || cus < 1) return SW2D_EINVAL;
+    if (per_cu > kBatchWgPerCu) per_cu = kBatchWgPerCu;
+    int g = cus * per_cu;
+    if (g > kMaxBatchGrid) g = kMaxBatchGrid;
+    *out = g;
     return SW2D_OK;
 }
 
@@ -498,9 +614,9 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return fail(batch_hip_fail(e, "sw2d_batch_create"));
 
-    std::vector<BatchInst> inst(n);
-    std::vector<BatchTile> tiles;
-    tiles.reserve(L.n_tiles);
+    b->inst.assign(n, BatchInst{});
+    b->rows.assign(n, 0);
+    b->tile_capacity = (size_t)L.n_tiles;
     for (int i = 0; i < n; ++i) {
         if (flags[i].bad != 0 || flags[i].hmax_bits == 0) return fail(SW2D_EINVAL);
         float hmax;
@@ -509,50 +625,26 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
         const double courant =
             q.dt * std::sqrt(q.g * (double)hmax) * std::sqrt(1.0 / (q.dx * q.dx) + 1.0 / (q.dy * q.dy));
         if (!(courant <= 1.0)) return fail(SW2D_EINVAL);
-        BatchInst& in = inst[i];
+        BatchInst& in = b->inst[i];
         in.hp = reinterpret_cast<const float*>(w + L.hp[i]);
         const size_t cells = (size_t)q.nx * q.ny;
         for (int buf = 0; buf < 2; ++buf)
             for (int f = 0; f < 3; ++f) in.state[buf][f] = d_state[i] + (size_t)(3 * buf + f) * cells;
         in.nx = q.nx;
         in.ny = q.ny;
-        in.strips = (q.nx + kStripOut - 1) / kStripOut;
         in.k = sw2d::detail::make_coef(&q);
         in.cell_area = q.dx * q.dy;
         in.h_sum = flags[i].h_sum;
-        in.tile_begin = (int)tiles.size();
-        const int rows = rows_for(q, band_rows, i);
-        const int groups = (in.strips + kWavesPerGroup - 1) / kWavesPerGroup;
-        const int bands = (q.ny + rows - 1) / rows;
-        for (int blk = 0; blk < bands; blk += 2)
-            for (int gr = 0; gr < groups; ++gr)
-                for (int bd = blk; bd < blk + 2 && bd < bands; ++bd) {
-                    BatchTile t;
-                    std::memset(&t, 0, sizeof t);
-                    t.hp = in.hp;
-                    for (int buf = 0; buf < 2; ++buf)
-                        for (int f = 0; f < 3; ++f) t.state[buf][f] = in.state[buf][f];
-                    t.nx = q.nx;
-                    t.ny = q.ny;
-                    t.strips = in.strips;
-                    t.j0 = bd * rows;
-                    t.j1 = (t.j0 + rows < q.ny) ? t.j0 + rows : q.ny;
-                    t.group2 = 2 * gr + (bd & 1);
-                    t.inst = i;
-                    t.k = in.k;
-                    tiles.push_back(t);
-                }
-        in.tile_end = (int)tiles.size();
+        b->rows[i] = rows_for(q, band_rows, i);
     }
+    b->steps_per_pass = 1;
+    b->passes_done = 0;
+    int rc = upload_tiles(b, 1);
+    if (rc) return fail(rc);
     BatchControl ctl;
     std::memset(&ctl, 0, sizeof ctl);
     std::vector<unsigned long long> zero_flags((size_t)kMaxBatchGrid * kFlagStride, 0ull);
-    e = hipMemcpyAsync(b->d_inst, inst.data(), n * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
-                           b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, b->stream);
+    e = hipMemcpyAsync(b->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_flags, zero_flags.data(), zero_flags.size() * sizeof(unsigned long long),
                            hipMemcpyHostToDevice, b->stream);
@@ -560,17 +652,12 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     if (e != hipSuccess) return fail(batch_hip_fail(e, "sw2d_batch_create upload"));
 
     // persistent grid: no more workgroups than the device can hold at once
-    int dev = 0, cus = 0, per_cu = 0, clock_khz = 0;
+    int dev = 0, clock_khz = 0;
     e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sw2d_batch_kernel, kBatchThreads, 0);
-    if (e != hipSuccess) return fail(batch_hip_fail(e, "occupancy query"));
-    if (per_cu < 1 || cus < 1) return fail(SW2D_EINVAL);
-    if (per_cu > kBatchWgPerCu) per_cu = kBatchWgPerCu;
-    b->max_grid = cus * per_cu;
-    if (b->max_grid > kMaxBatchGrid) b->max_grid = kMaxBatchGrid;
+    if (e != hipSuccess) return fail(batch_hip_fail(e, "device query"));
+    rc = resident_grid(1, &b->max_grid);
+    if (rc) return fail(rc);
     b->grid = b->max_grid;
     if (clock_khz <= 0) clock_khz = 100000;
     b->timeout_ticks = (unsigned long long)clock_khz * 1000ull * 2ull;  // 2 s per barrier
@@ -579,6 +666,25 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     *out = b;
     return SW2D_OK;
 }
+
+int sw2d_batch_set_time_blocking(sw2d_batch_t b, int32_t steps_per_pass) {
+    if (!b) return SW2D_ESTATE;
+    if (steps_per_pass < 1 || steps_per_pass > kMaxBatchK) return SW2D_EINVAL;
+    if (steps_per_pass == b->steps_per_pass) return SW2D_OK;
+    SW2D_BHIP(hipStreamSynchronize(b->stream));  // launches in flight read the old tile list
+    int max_grid = 0;
+    int rc = resident_grid(steps_per_pass, &max_grid);
+    if (rc) return rc;
+    rc = upload_tiles(b, steps_per_pass);
+    if (rc) return rc;
+    b->steps_per_pass = steps_per_pass;
+    b->max_grid = max_grid;
+    if (b->grid > max_grid || b->grid <= 0) b->grid = max_grid;
+    drop_graph(b);
+    return SW2D_OK;
+}
+
+int32_t sw2d_batch_time_blocking(sw2d_batch_t b) { return b ? b->steps_per_pass : -1; }
 
 int sw2d_batch_set_launch(sw2d_batch_t b, int32_t steps_per_launch, int32_t use_graph, int32_t grid) {
     if (!b) return SW2D_ESTATE;
@@ -594,6 +700,7 @@ int sw2d_batch_set_launch(sw2d_batch_t b, int32_t steps_per_launch, int32_t use_
 int sw2d_batch_step(sw2d_batch_t b, int32_t nsteps) {
     if (!b || nsteps < 0) return SW2D_ESTATE;
     if (nsteps == 0) return SW2D_OK;
+    if (nsteps % b->steps_per_pass != 0) return SW2D_EINVAL;
     if (!b->use_graph) {
         int rc = enqueue_chunks(b, nsteps, b->stream);
         if (rc) return rc;
@@ -620,6 +727,7 @@ int sw2d_batch_step(sw2d_batch_t b, int32_t nsteps) {
         SW2D_BHIP(hipGraphLaunch(b->exec, b->stream));
     }
     b->steps_done += nsteps;
+    b->passes_done += nsteps / b->steps_per_pass;
     return SW2D_OK;
 }
 
@@ -674,7 +782,7 @@ int sw2d_batch_reduce(sw2d_batch_t b, sw2d_red* host_out) {
 
 int sw2d_batch_state(sw2d_batch_t b, int32_t k, float** d_eta, float** d_u, float** d_v) {
     if (!b || k < 0 || k >= b->n) return SW2D_ESTATE;
-    const int cur = (int)(b->steps_done & 1);
+    const int cur = (int)(b->passes_done & 1);
     float* const* s = &b->state[(size_t)k * 6 + 3 * cur];
     if (d_eta) *d_eta = s[0];
     if (d_u) *d_u = s[1];

@@ -222,6 +222,15 @@ class Sw2dBatch:
         check(_lib.load().sw2d_batch_set_barrier_timeout(self._handle(), float(seconds)),
               "sw2d_batch_set_barrier_timeout")
 
+    def set_time_blocking(self, steps_per_pass: int):
+        """K = 1..3 steps per pass; sw2d_batch_step then takes multiples of K."""
+        check(_lib.load().sw2d_batch_set_time_blocking(self._handle(), int(steps_per_pass)),
+              "sw2d_batch_set_time_blocking")
+
+    @property
+    def time_blocking(self) -> int:
+        return int(_lib.load().sw2d_batch_time_blocking(self._handle()))
+
     @property
     def grid(self) -> int:
         return int(_lib.load().sw2d_batch_grid(self._handle()))

@@ -137,3 +137,51 @@ def test_autotuner_parity_guard_and_cache(tmp_path):
     assert len(rows) == 4 and all(r in (8, 16, 32) for r in rows)
     again = autotune.tune(cases, candidates=(8, 16, 32), cache_path=path, steps=5, warmup=2)
     assert again == rows
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_multi_step_passes_equal_single_runs(K):
+    """K steps per pass in the batched kernel: every instance bitwise equal to single steps,
+    the folds of every step kept (the last K ring entries checked against single runs)."""
+    cases = _cases(SHAPES)
+    rows = [8, 16, 24, 8, 32, 8, 16, 64, 8, 16, 8, 8]
+    n = 12 * K
+    with Sw2dBatch(cases, band_rows=rows) as b:
+        b.set_time_blocking(K)
+        assert b.time_blocking == K
+        b.set_launch(steps_per_launch=5 * K, use_graph=True)
+        b.step(n - 2 * K)
+        b.step(K)
+        b.step(K)
+        red = b.reduce()
+        states = [b.state_numpy(k) for k in range(b.n)]
+        with pytest.raises(_lib.Sw2dError):
+            b.step(K + 1)
+    assert (red["step"] == n).all()
+    for k, c in enumerate(cases):
+        e, u, v, sred = gpu_run(c, nsteps=n, k=1)
+        for g, s in zip(states[k], (e, u, v)):
+            assert np.array_equal(g, s), f"K={K} instance {k} {c.nx}x{c.ny}"
+        np.testing.assert_allclose(red["vol_disp"][k], sred["vol_disp"][-1], rtol=1e-12,
+                                   atol=1e-9 * c.dx * c.dy)
+        assert red["max_abs_u"][k] == sred["max_abs_u"][-1]
+        assert red["max_abs_v"][k] == sred["max_abs_v"][-1]
+
+
+def test_switching_steps_per_pass_mid_run():
+    cases = _cases(SHAPES[:6], steps=30)
+    with Sw2dBatch(cases) as b:
+        b.step(5)
+        b.set_time_blocking(3)
+        b.step(9)
+        b.set_time_blocking(2)
+        b.step(4)
+        b.set_time_blocking(1)
+        b.step(3)
+        states = [b.state_numpy(k) for k in range(b.n)]
+        red = b.reduce()
+    assert (red["step"] == 21).all()
+    for k, c in enumerate(cases):
+        e, u, v, _ = gpu_run(c, nsteps=21, k=1)
+        for g, s in zip(states[k], (e, u, v)):
+            assert np.array_equal(g, s), k
