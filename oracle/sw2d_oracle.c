@@ -30,7 +30,11 @@
  *    likewise; and the Shapiro filter applied to the predicted velocities as well,
  *        u' = us + (eps/4) * sum over active neighbouring u faces (us_nb - us)
  *    (neighbours east, west, north, south), v' likewise, after the surface update
- *    used the unfiltered us, vs.
+ *    used the unfiltered us, vs; and nonlinear momentum advection, first-order upwind,
+ *        us -= dt (u du/dx + vbar du/dy),  vs -= dt (ubar dv/dx + v dv/dy),
+ *    each derivative a one-sided difference on the upstream side of its advecting
+ *    velocity, vbar the mean of the four v faces around the u face and ubar likewise,
+ *    neighbours off the grid or on inactive faces counted as 0.
  *  - Per-step folds: V_disp = dx dy sum_wet eta', V_tot = dx dy sum_wet (H + eta'),
  *    max|u'|, max|v'|. The paper's compiler turns loop nests into maps and
  *    these reductions into folds (Sect. 4.3).
@@ -56,6 +60,37 @@ static int is_wet(const unsigned char *mask, int nx, int ny, int j, int i) {
 
 #define SW2D_ORACLE_FRICTION 1
 #define SW2D_ORACLE_FILTER_UV 2
+#define SW2D_ORACLE_ADVECTION 4
+
+/* a face value, 0 off the grid */
+static double face_at(const double *a, int nx, int ny, int j, int i) {
+    if (i < 0 || j < 0 || i >= nx || j >= ny) return 0.0;
+    return AT(a, j, i);
+}
+
+/* first-order upwind advection of the u face (j,i): u du/dx + vbar du/dy */
+static double advect_u(const double *u, const double *v, int nx, int ny, int j, int i, double dx, double dy) {
+    const double c = AT(u, j, i);
+    const double vbar = 0.25 * ((face_at(v, nx, ny, j, i) + face_at(v, nx, ny, j, i + 1)) +
+                                (face_at(v, nx, ny, j - 1, i) + face_at(v, nx, ny, j - 1, i + 1)));
+    const double ax = c > 0.0 ? c * (c - face_at(u, nx, ny, j, i - 1)) / dx
+                              : c * (face_at(u, nx, ny, j, i + 1) - c) / dx;
+    const double ay = vbar > 0.0 ? vbar * (c - face_at(u, nx, ny, j - 1, i)) / dy
+                                 : vbar * (face_at(u, nx, ny, j + 1, i) - c) / dy;
+    return ax + ay;
+}
+
+/* first-order upwind advection of the v face (j,i): ubar dv/dx + v dv/dy */
+static double advect_v(const double *u, const double *v, int nx, int ny, int j, int i, double dx, double dy) {
+    const double c = AT(v, j, i);
+    const double ubar = 0.25 * ((face_at(u, nx, ny, j, i) + face_at(u, nx, ny, j, i - 1)) +
+                                (face_at(u, nx, ny, j + 1, i) + face_at(u, nx, ny, j + 1, i - 1)));
+    const double bx = ubar > 0.0 ? ubar * (c - face_at(v, nx, ny, j, i - 1)) / dx
+                                 : ubar * (face_at(v, nx, ny, j, i + 1) - c) / dx;
+    const double by = c > 0.0 ? c * (c - face_at(v, nx, ny, j - 1, i)) / dy
+                              : c * (face_at(v, nx, ny, j + 1, i) - c) / dy;
+    return bx + by;
+}
 
 /* active u face (east face of cell j,i) and active v face (north face) */
 static int u_face(const unsigned char *mask, int nx, int ny, int j, int i) {
@@ -87,7 +122,8 @@ static void filter_faces(int nx, int ny, double e4, const unsigned char *mask, c
 }
 
 /* One step. scratch holds 3*nx*ny doubles (Fx, Fy, es). flags: SW2D_ORACLE_FRICTION
- * (quadratic bottom friction with coefficient cd), SW2D_ORACLE_FILTER_UV. Returns 0, or 1
+ * (quadratic bottom friction with coefficient cd), SW2D_ORACLE_FILTER_UV,
+ * SW2D_ORACLE_ADVECTION. Returns 0, or 1
  * if a water cell has non-positive total depth H + eta (the model has no drying). */
 int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, double eps,
                      const double *H, const unsigned char *mask,
@@ -119,6 +155,7 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
             double us = 0.0, vs = 0.0, fx = 0.0, fy = 0.0;
             if (au) {
                 us = AT(u, j, i) - cx * (AT(eta, j, i + 1) - AT(eta, j, i));
+                if (flags & SW2D_ORACLE_ADVECTION) us = us - dt * advect_u(u, v, nx, ny, j, i, dx, dy);
                 if (flags & SW2D_ORACLE_FRICTION) {
                     double hf = 0.5 * ((AT(H, j, i) + AT(eta, j, i)) + (AT(H, j, i + 1) + AT(eta, j, i + 1)));
                     us = us / (1.0 + kf * fabs(AT(u, j, i)) / hf);
@@ -129,6 +166,7 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
             }
             if (av) {
                 vs = AT(v, j, i) - cy * (AT(eta, j + 1, i) - AT(eta, j, i));
+                if (flags & SW2D_ORACLE_ADVECTION) vs = vs - dt * advect_v(u, v, nx, ny, j, i, dx, dy);
                 if (flags & SW2D_ORACLE_FRICTION) {
                     double hf = 0.5 * ((AT(H, j, i) + AT(eta, j, i)) + (AT(H, j + 1, i) + AT(eta, j + 1, i)));
                     vs = vs / (1.0 + kf * fabs(AT(v, j, i)) / hf);

@@ -81,12 +81,13 @@ class DryCellError(RuntimeError):
 
 FRICTION = 1   # quadratic bottom friction on the predictor (coefficient cd)
 FILTER_UV = 2  # the Shapiro filter on the predicted velocities as well
+ADVECTION = 4  # first-order upwind momentum advection in the predictor
 
 
 def run(nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, nsteps, nthreads=1, reductions=True, flags=0, cd=0.0):
     """Advance ``nsteps`` steps in FP64. Returns (eta, u, v, red) with red[s] = (V_tot, V_disp,
     max|u|, max|v|) after step s, or None when ``reductions`` is False. ``flags`` selects the
-    model variants (FRICTION with coefficient ``cd``, FILTER_UV)."""
+    model variants (FRICTION with coefficient ``cd``, FILTER_UV, ADVECTION)."""
     lib = _load()
     H, mask = _f64(H), _u8(mask)
     eta, u, v = _f64(eta).copy(), _f64(u).copy(), _f64(v).copy()

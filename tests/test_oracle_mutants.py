@@ -35,6 +35,14 @@ MUTANTS = {
     "friction_one_sided_depth": ("double hf = 0.5 * ((AT(H, j, i) + AT(eta, j, i)) + (AT(H, j, i + 1) + AT(eta, j, i + 1)));",
                                  "double hf = AT(H, j, i) + AT(eta, j, i);"),
     "uv_filter_over_inactive_faces": ("if (act(mask, nx, ny, j + 1, i)) s += AT(a, j + 1, i) - c;", "s += AT(a, j + 1, i) - c;"),
+    "advection_downwind_x": ("const double ax = c > 0.0 ? c * (c - face_at(u, nx, ny, j, i - 1)) / dx",
+                             "const double ax = c < 0.0 ? c * (c - face_at(u, nx, ny, j, i - 1)) / dx"),
+    "advection_vbar_drops_a_face": ("(face_at(v, nx, ny, j - 1, i) + face_at(v, nx, ny, j - 1, i + 1)));",
+                                    "(face_at(v, nx, ny, j - 1, i) + 0.0));"),
+    "advection_dy_by_dx": ("                                 : vbar * (face_at(u, nx, ny, j + 1, i) - c) / dy;",
+                           "                                 : vbar * (face_at(u, nx, ny, j + 1, i) - c) / dx;"),
+    "advection_v_wrong_neighbour": ("const double by = c > 0.0 ? c * (c - face_at(v, nx, ny, j - 1, i)) / dy",
+                                    "const double by = c > 0.0 ? c * (c - face_at(v, nx, ny, j, i - 1)) / dy"),
     "uv_filter_v_on_u_faces": ("filter_faces(nx, ny, e4, mask, v_out, Fy, v_face);", "filter_faces(nx, ny, e4, mask, v_out, Fy, u_face);"),
 }
 
@@ -81,6 +89,9 @@ def _pin_variants():
     for k, l in ((1, 0), (2, 3)):
         tv.test_velocity_filter_modes_decay_by_the_closed_form(k, l)
     tv.test_velocity_filter_conserves_the_face_sum_and_follows_the_surface_update()
+    for a in (0.03, -0.05):
+        tv.test_advection_of_linear_profiles_is_exact(a)
+    tv.test_advection_keeps_mirror_and_transpose_symmetry()
 
 
 PINS = (_pin_golden, _pin_modes, _pin_exact, _pin_volume, _pin_variants)

@@ -142,3 +142,79 @@ def test_variants_keep_lake_at_rest_and_volume(flags):
     bump = eta + 0.3 * np.exp(-((np.arange(nx)[None] - 14) ** 2 + (np.arange(ny)[:, None] - 6) ** 2) / 8.0) * mask
     e, u, v, red = sw2d_ref.run(nx, ny, 100.0, 100.0, 9.81, 1.5, 0.1, H, mask, bump, z, z, 60, flags=flags, cd=0.003)
     assert abs(red[-1, 1] - red[0, 1]) <= 1e-12 * abs(red[0, 1])
+
+
+AD = sw2d_ref.ADVECTION
+
+
+def _channel(nx, ny):
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[1:-1, 1:-1] = 1
+    return np.full((ny, nx), 10.0) * mask, mask
+
+
+@pytest.mark.parametrize("a", [0.03, -0.05])
+def test_advection_of_linear_profiles_is_exact(a):
+    """Away from the walls a one-sided difference of a linear profile is its slope, on
+    either side: u = a i + b (v = 0) gives us = u - dt u a / dx; u = a j with v = V gives
+    us = u - dt V a / dy; v = a j gives vs = v - dt v a / dy; v = a i with u = U gives
+    vs = v - dt U a / dx. A level surface, so no pressure gradient."""
+    nx, ny, dx, dy, dt = 24, 20, 100.0, 70.0, 3.0
+    H, mask = _channel(nx, ny)
+    au, av = _faces(mask)
+    eta = np.zeros((ny, nx))
+    jj, ii = np.mgrid[0:ny, 0:nx].astype(float)
+    # interior faces: all neighbouring faces (and the four around) active
+    inner = np.zeros((ny, nx), bool)
+    inner[3:-3, 3:-3] = True
+    run = lambda u, v: sw2d_ref.run(nx, ny, dx, dy, 9.81, dt, 0.0, H, mask, eta, u, v, 1, flags=AD)
+    # u linear in i, v = 0
+    u = (a * ii + 0.1) * au
+    _, u1, _, _ = run(u, np.zeros_like(u))
+    np.testing.assert_allclose(u1[inner & au], (u - dt * u * a / dx)[inner & au], rtol=1e-13, atol=1e-16)
+    # u linear in j advected by a uniform v (either sign)
+    for V in (0.2, -0.25):
+        u = (a * jj + 0.05) * au
+        v = V * av
+        _, u1, v1, _ = run(u, v)
+        np.testing.assert_allclose(u1[inner & au], (u - dt * V * a / dy)[inner & au], rtol=1e-13, atol=1e-16)
+    # v linear in j, u = 0
+    v = (a * jj - 0.1) * av
+    _, _, v1, _ = run(np.zeros_like(v), v)
+    np.testing.assert_allclose(v1[inner & av], (v - dt * v * a / dy)[inner & av], rtol=1e-13, atol=1e-16)
+    # v linear in i advected by a uniform u (either sign)
+    for U in (-0.15, 0.3):
+        v = (a * ii + 0.02) * av
+        u = U * au
+        _, u1, v1, _ = run(u, v)
+        np.testing.assert_allclose(v1[inner & av], (v - dt * U * a / dx)[inner & av], rtol=1e-13, atol=1e-16)
+
+
+def test_advection_keeps_mirror_and_transpose_symmetry():
+    from paper_1711_04471_amd import inputs
+    c = inputs.small_basin(41, 36, seed=17, steps=20)
+    c.dy, c.dt = 0.7 * c.dx, 0.7 * c.dt  # anisotropic, so the transpose tells dx from dy
+    rng = np.random.Generator(np.random.PCG64(71))
+    au, av = _faces(c.mask)
+    c.u = (rng.uniform(-0.3, 0.3, c.u.shape) * au).astype(np.float32)
+    c.v = (rng.uniform(-0.3, 0.3, c.v.shape) * av).astype(np.float32)
+    e, u, v, _ = sw2d_ref.run_case(c, flags=AD)
+    # mirror in x: eta(i) -> eta(nx-1-i), u on east faces (i) -> -u(nx-2-i), v(i) -> v(nx-1-i)
+    mu0 = np.zeros_like(c.u)
+    mu0[:, :-1] = -c.u[:, -2::-1]
+    me, mu, mv, _ = sw2d_ref.run(c.nx, c.ny, c.dx, c.dy, c.g, c.dt, c.eps, c.H[:, ::-1], c.mask[:, ::-1],
+                                 c.eta[:, ::-1], mu0, c.v[:, ::-1], c.steps, flags=AD)
+    np.testing.assert_allclose(me[:, ::-1], e, rtol=0, atol=1e-13 * np.abs(e).max())
+    np.testing.assert_allclose(-mu[:, -2::-1], u[:, :-1], rtol=0, atol=1e-13 * np.abs(u).max())
+    np.testing.assert_allclose(mv[:, ::-1], v, rtol=0, atol=1e-13 * np.abs(v).max())
+    # transpose: swap axes, u <-> v, dx <-> dy
+    te, tu, tv, _ = sw2d_ref.run(c.ny, c.nx, c.dy, c.dx, c.g, c.dt, c.eps, c.H.T, c.mask.T, c.eta.T,
+                                 c.v.T, c.u.T, c.steps, flags=AD)
+    np.testing.assert_allclose(te.T, e, rtol=0, atol=1e-13 * np.abs(e).max())
+    np.testing.assert_allclose(tv.T, u, rtol=0, atol=1e-13 * np.abs(u).max())
+    np.testing.assert_allclose(tu.T, v, rtol=0, atol=1e-13 * np.abs(v).max())
+
+
+@pytest.mark.parametrize("flags", [AD, AD | FR | UV])
+def test_advection_keeps_lake_at_rest_and_volume(flags):
+    test_variants_keep_lake_at_rest_and_volume(flags)
