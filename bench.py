@@ -293,12 +293,12 @@ def variants_leg(case, steps, log):
     both) on the same basin: same 28 B per cell-step, more arithmetic per cell."""
     import torch
 
-    from paper_1711_04471_amd.sw2d import FILTER_UV, FRICTION, Sw2d
+    from paper_1711_04471_amd.sw2d import ADVECTION, FILTER_UV, FRICTION, Sw2d
 
     out = {}
     cells = case.nx * case.ny
     for name, flags in (("plain", 0), ("friction", FRICTION), ("filter_uv", FILTER_UV),
-                        ("friction+filter_uv", FRICTION | FILTER_UV)):
+                        ("advection", ADVECTION), ("all", FRICTION | FILTER_UV | ADVECTION)):
         with Sw2d.from_case(case, flags=flags, cd=0.0025) as sim:
             sim.band_rows = 16
             sim.step(10)

@@ -62,14 +62,21 @@ enum {
  *                  velocities as well: u' = us + eps/4 sum over active neighbouring u faces
  *                  (east, west, north, south) of (us_nb - us); v' likewise. The surface update
  *                  of the step uses the unfiltered us, vs.
+ *  SW2D_ADVECTION: nonlinear momentum advection, first-order upwind, in the predictor:
+ *                  us -= dt (u du/dx + vbar du/dy), vs -= dt (ubar dv/dx + v dv/dy), each
+ *                  derivative a one-sided difference on the upstream side of its advecting
+ *                  velocity (u > 0: backward), vbar the mean of the four v faces around the
+ *                  u face, ubar likewise; faces off the grid or inactive count as 0. Applied
+ *                  before the friction division.
  * A handle with flags steps one step per pass (sw2d_set_time_blocking refuses K > 1), and
  * the batched and unfused paths take flags = 0 only. */
 #define SW2D_FRICTION 1u
 #define SW2D_FILTER_UV 2u
+#define SW2D_ADVECTION 4u
 
 /* Grid and constants. nx, ny count every cell, land border included (>= 3 each).
  * dx, dy, dt > 0 and finite; g >= 0 and finite; eps in [0, 1] (Shapiro weight);
- * flags: 0 or a combination of SW2D_FRICTION and SW2D_FILTER_UV; cd >= 0 and finite, the
+ * flags: 0 or a combination of SW2D_FRICTION, SW2D_FILTER_UV, SW2D_ADVECTION; cd >= 0 and finite, the
  * bottom-drag coefficient (used with SW2D_FRICTION, ignored otherwise). */
 typedef struct {
     int32_t nx, ny;

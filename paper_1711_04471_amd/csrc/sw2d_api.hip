@@ -63,7 +63,7 @@ bool params_ok(const sw2d_params* p) {
     if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dt)) return false;
     if (!std::isfinite(p->g) || p->g < 0.0) return false;
     if (!std::isfinite(p->eps) || p->eps < 0.0 || p->eps > 1.0) return false;
-    if (p->flags & ~(uint32_t)(SW2D_FRICTION | SW2D_FILTER_UV)) return false;
+    if (p->flags & ~(uint32_t)(SW2D_FRICTION | SW2D_FILTER_UV | SW2D_ADVECTION)) return false;
     if (!std::isfinite(p->cd) || p->cd < 0.0) return false;
     return true;
 }
@@ -220,7 +220,7 @@ int sw2d_create(const sw2d_params* p, const float* d_H, const uint8_t* d_mask, f
     h->ring = reinterpret_cast<sw2d_red*>(w + L.ring);
     h->part = reinterpret_cast<FoldPartial*>(w + L.part);
     h->part_capacity = L.part_capacity;
-    h->geo = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny));
+    h->geo = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny), single_strip_out(p->flags));
     for (int K = 2; K <= kMaxStepsPerPass; ++K)
         h->geok[K] = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny), strip_out_for(K));
     h->steps_per_pass = 1;
@@ -316,7 +316,7 @@ int sw2d_step_unfused(sw2d_t h, int32_t nsteps, float* d_scratch, size_t scratch
 int sw2d_set_band_rows(sw2d_t h, int32_t rows) {
     if (!h) return SW2D_ESTATE;
     if (rows < kMinRows || rows > h->p.ny) return SW2D_EINVAL;
-    h->geo = make_geometry(h->p.nx, h->p.ny, rows);
+    h->geo = make_geometry(h->p.nx, h->p.ny, rows, single_strip_out(h->p.flags));
     return SW2D_OK;
 }
 

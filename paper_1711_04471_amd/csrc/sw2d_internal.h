@@ -50,7 +50,17 @@ struct StepCoef {
 };
 
 // Model variants of the step (the flags of sw2d_params), as template arguments.
-enum : int { kVarFriction = 1, kVarFilterUV = 2, kVarAll = kVarFriction | kVarFilterUV };
+enum : int {
+    kVarFriction = 1,
+    kVarFilterUV = 2,
+    kVarAdvection = 4,
+    kVarAll = kVarFriction | kVarFilterUV | kVarAdvection
+};
+// With advection the single-step strip keeps a 3-lane halo on its west side (the x-face
+// predictor reads u one face further west) and 2 on its east side: 59 owned columns.
+constexpr int kAdvHaloW = 3;
+constexpr int kAdvStripOut = kWave - kAdvHaloW - kHalo;
+constexpr int single_strip_out(uint32_t flags) { return (flags & kVarAdvection) ? kAdvStripOut : kStripOut; }
 
 enum : uint32_t {
     kWetBorder = 1u,

@@ -123,18 +123,24 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
     const int band = tile / geo.groups_x;
     const int group = tile - band * geo.groups_x;
 #endif
+    constexpr bool kAdv = (kVar & kVarAdvection) != 0;
+    constexpr int kOut = kAdv ? kAdvStripOut : kStripOut;
+    constexpr int kWest = kAdv ? kAdvHaloW : kHalo;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     const int strip = group * kWavesPerGroup + wave;
-    const int c = strip * kStripOut - kHalo + lane;
+    const int c = strip * kOut - kWest + lane;
     const bool col_in = c >= 0 && c < geo.nx;
-    const bool out_lane = col_in && lane >= kHalo && lane < kWave - kHalo;
+    const bool out_lane = col_in && lane >= kWest && lane < kWest + kOut;
     const int j0 = band * geo.rows;
     const int j1 = min(j0 + geo.rows, geo.ny);
 
     double f_disp = 0.0;
     float f_mu = 0.f, f_mv = 0.f;
-    if (strip < geo.strips) {
+    if (kAdv && strip < geo.strips) {
+        march_adv<kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k, f_disp,
+                        f_mu, f_mv);
+    } else if (strip < geo.strips) {
 #if SW2D_ZIGZAG
         // Odd bands march south, so each band boundary is read by both of its bands at
         // the same moment (both at their start or both at their end) and the second
@@ -306,25 +312,23 @@ hipError_t launch_step(int kvar, const float* eta, const float* u, const float* 
                        float* eta_o, float* u_o, float* v_o, FoldPartial* part,
                        const StepGeometry& geo, const StepCoef& k, hipStream_t s) {
     const dim3 grid(geo.nblocks), block(kGroupThreads);
+#define SW2D_STEP_CASE(V)                                                                                   \
+    case V:                                                                                                 \
+        hipLaunchKernelGGL(sw2d_step_kernel<V>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, geo, k); \
+        break;
     switch (kvar) {
-        case 0:
-            hipLaunchKernelGGL(sw2d_step_kernel<0>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, geo, k);
-            break;
-        case kVarFriction:
-            hipLaunchKernelGGL(sw2d_step_kernel<kVarFriction>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o,
-                               part, geo, k);
-            break;
-        case kVarFilterUV:
-            hipLaunchKernelGGL(sw2d_step_kernel<kVarFilterUV>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o,
-                               part, geo, k);
-            break;
-        case kVarAll:
-            hipLaunchKernelGGL(sw2d_step_kernel<kVarAll>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part,
-                               geo, k);
-            break;
+        SW2D_STEP_CASE(0)
+        SW2D_STEP_CASE(1)
+        SW2D_STEP_CASE(2)
+        SW2D_STEP_CASE(3)
+        SW2D_STEP_CASE(4)
+        SW2D_STEP_CASE(5)
+        SW2D_STEP_CASE(6)
+        SW2D_STEP_CASE(7)
         default:
             return hipErrorInvalidValue;
     }
+#undef SW2D_STEP_CASE
     return hipGetLastError();
 }
 

@@ -238,6 +238,102 @@ struct Stage {
     }
 };
 
+// ---------------------------------------------------------------------------------------
+// Variant with nonlinear momentum advection (first-order upwind). The x-face predictor of a
+// row needs u of the rows above and below it, so the pipeline computes it one row later
+// than the plain Stage: push(row r) predicts the x-faces of row r-1 and the y-face r-1|r,
+// completes es of row r-1 and returns row r-2 as before. The y-face's upwind difference
+// reads v one row further south, so a band starts 3 rows below its first output row and
+// marches north only; the x-face reads u one face further west, so strips keep 3 halo
+// lanes on their west side.
+template <int kVar>
+struct StageAdv {
+    static constexpr bool kFilterUV = (kVar & kVarFilterUV) != 0;
+    // row r-1
+    float e1 = 0.f, h1 = 0.f, hp1 = 0.f, u1 = 0.f, v1 = 0.f;
+    bool w1 = false, wE1 = false, wW1 = false;
+    // row r-2 (and the faces computed at the previous push)
+    float u2 = 0.f, v2 = 0.f, es2 = 0.f, fy2 = 0.f, us2 = 0.f, vs2 = 0.f, hp2 = 0.f;
+    bool w2 = false, wE2 = false, wW2 = false, au2 = false, av2 = false;
+    // row r-3
+    float es3 = 0.f, us3 = 0.f, vs3 = 0.f;
+    bool w3 = false, au3 = false, av3 = false;
+
+    __device__ __forceinline__ void push(float e, float hpr, float ur, float vr, const StepCoef& k,
+                                         float& eta_o, float& u_o, float& v_o, float& hp_o) {
+#pragma clang fp contract(off)
+        const bool w = hpr > 0.f;
+        const float h = hpr + e;
+        const bool wE = from_east(hpr) > 0.f;
+        const bool wW = from_west(hpr) > 0.f;
+        // x-faces of row r-1: pressure gradient, advection, friction; flux and partial update
+        const float eE1 = from_east(e1), hpE1 = from_east(hp1);
+        // Lane exchanges are taken by every lane before any select: a DPP read from a lane
+        // that sits out a divergent branch returns 0, not its value.
+        const float uW1 = from_west(u1), uE1 = from_east(u1), vW1 = from_west(v1), vE1 = from_east(v1);
+        const float uWr = from_west(ur);
+        const bool au1 = w1 && wE1;
+        const float vbar = 0.25f * ((v1 + vE1) + (v2 + from_east(v2)));
+        // dt (u du/dx + vbar du/dy) = (u du) dt/dx + (vbar du) dt/dy, upstream differences
+        const float tx = u1 > 0.f ? u1 * (u1 - uW1) : u1 * (uE1 - u1);
+        const float ty = vbar > 0.f ? vbar * (u1 - u2) : vbar * (ur - u1);
+        float pu = fmaf(-k.cx, eE1 - e1, u1);
+        pu = pu - (tx * k.rx + ty * k.ry);
+        if constexpr ((kVar & kVarFriction) != 0) pu = friction(pu, u1, h1, hpE1 + eE1, k);
+        const float us1 = au1 ? pu : 0.f;
+        const float fx1 = us1 * (us1 > 0.f ? h1 : hpE1 + eE1);
+        const float pe1 = fmaf(-k.rx, fx1 - from_west(fx1), e1);
+        // y-face r-1|r
+        const bool av = w1 && w;
+        const float ubar = 0.25f * ((u1 + uW1) + (ur + uWr));
+        const float tbx = ubar > 0.f ? ubar * (v1 - vW1) : ubar * (vE1 - v1);
+        const float tby = v1 > 0.f ? v1 * (v1 - v2) : v1 * (vr - v1);
+        float pv = fmaf(-k.cy, e - e1, v1);
+        pv = pv - (tbx * k.rx + tby * k.ry);
+        if constexpr ((kVar & kVarFriction) != 0) pv = friction(pv, v1, h1, h, k);
+        const float vs = av ? pv : 0.f;
+        const float fy = vs * (vs > 0.f ? h1 : h);
+        // surface of row r-1, then the output row r-2
+        const float es = w1 ? fmaf(-k.ry, fy - fy2, pe1) : 0.f;
+        eta_o = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
+        if constexpr (kFilterUV) {
+            u_o = shapiro_face(us2, au2, us1, au1, us3, au3, k.e4);
+            v_o = shapiro_face(vs2, av2, vs, av, vs3, av3, k.e4);
+        } else {
+            u_o = us2;
+            v_o = vs2;
+        }
+        hp_o = hp2;
+        // shift: rows r-2 -> r-3, r-1 -> r-2, r -> r-1
+        es3 = es2;
+        w3 = w2;
+        us3 = us2;
+        au3 = au2;
+        vs3 = vs2;
+        av3 = av2;
+        es2 = es;
+        fy2 = fy;
+        us2 = us1;
+        au2 = au1;
+        vs2 = vs;
+        av2 = av;
+        hp2 = hp1;
+        w2 = w1;
+        wE2 = wE1;
+        wW2 = wW1;
+        u2 = u1;
+        v2 = v1;
+        e1 = e;
+        h1 = h;
+        hp1 = hpr;
+        u1 = ur;
+        v1 = vr;
+        w1 = w;
+        wE1 = wE;
+        wW1 = wW;
+    }
+};
+
 #if SW2D_BUFFER_IO
 // Rows go through buffer resources: one per field and row, whose size is the row's bytes,
 // or zero for a row outside the grid. The hardware returns 0 for a load outside the
@@ -384,6 +480,37 @@ __device__ __forceinline__ void march(const float* __restrict__ eta, const float
         A.push(e, hpr, ur, vr, k, en, un, vn, hn);
         if (i >= 4) {
             W.put(r - 2 * step, en, un, vn);
+            if (out_lane) F.add(en, un, vn);
+        }
+    }
+    f_disp = F.disp;
+    f_mu = F.mu();
+    f_mv = F.mv();
+}
+
+// One step of a band with the advection pipeline (north only): rows j0-3 .. j1+1.
+template <int kVar>
+__device__ __forceinline__ void march_adv(const float* __restrict__ eta, const float* __restrict__ u,
+                                          const float* __restrict__ v, const float* __restrict__ hp,
+                                          float* __restrict__ eta_o, float* __restrict__ u_o,
+                                          float* __restrict__ v_o, int nx, int ny, int c, bool col_in,
+                                          bool out_lane, int j0, int j1, const StepCoef& k, double& f_disp,
+                                          float& f_mu, float& f_mv) {
+    const int r_first = j0 - 3;
+    const int n_rows = j1 - j0 + 5;
+    RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
+    L.fill(r_first, 1, n_rows);
+    StageAdv<kVar> A;
+    LaneFolds F;
+    for (int i = 0; i < n_rows; ++i) {
+        const int r = r_first + i;
+        float e, hpr, ur, vr;
+        L.next(i, r, 1, n_rows, e, hpr, ur, vr);
+        float en, un, vn, hn;
+        A.push(e, hpr, ur, vr, k, en, un, vn, hn);
+        if (i >= 5) {
+            W.put(r - 2, en, un, vn);
             if (out_lane) F.add(en, un, vn);
         }
     }

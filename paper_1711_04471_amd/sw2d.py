@@ -17,6 +17,7 @@ RED_DTYPE = np.dtype([("step", np.int64), ("vol_total", np.float64), ("vol_disp"
 
 FRICTION = 1   # quadratic bottom friction on the predictor (coefficient cd)
 FILTER_UV = 2  # the Shapiro filter on the predicted velocities as well
+ADVECTION = 4  # first-order upwind momentum advection in the predictor
 
 
 def params(nx, ny, dx, dy, g, dt, eps, flags=0, cd=0.0) -> sw2d_params:

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import sw2d_ref
 from paper_1711_04471_amd import inputs
-from paper_1711_04471_amd.sw2d import FILTER_UV, FRICTION, Sw2d
+from paper_1711_04471_amd.sw2d import ADVECTION, FILTER_UV, FRICTION, Sw2d
 from tests.helpers import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -35,11 +35,33 @@ def _gpu(case, flags, n, band_rows=None):
     return e, u, v, red
 
 
-@pytest.mark.parametrize("flags", [FRICTION, FILTER_UV, FRICTION | FILTER_UV])
+def _stirred(c, seed, amp=0.5):
+    """Smooth random velocities on the active faces (advection needs a flow to act on)."""
+    rng = np.random.default_rng(seed)
+    wet = c.mask != 0
+    au = np.zeros_like(wet)
+    au[:, :-1] = wet[:, :-1] & wet[:, 1:]
+    av = np.zeros_like(wet)
+    av[:-1] = wet[:-1] & wet[1:]
+    jj, ii = np.mgrid[0:c.ny, 0:c.nx]
+    f = lambda: sum(rng.uniform(-1, 1) * np.sin(2 * np.pi * (rng.integers(1, 4) * ii / c.nx + rng.integers(1, 4) * jj / c.ny)
+                                                + rng.uniform(0, 6.3)) for _ in range(3))
+    c.u = (amp * f() * au).astype(np.float32)
+    c.v = (amp * f() * av).astype(np.float32)
+    return c
+
+
+ALL_FLAGS = [FRICTION, FILTER_UV, FRICTION | FILTER_UV, ADVECTION, ADVECTION | FRICTION, ADVECTION | FILTER_UV,
+             ADVECTION | FRICTION | FILTER_UV]
+
+
+@pytest.mark.parametrize("flags", ALL_FLAGS)
 @pytest.mark.parametrize("shape", [(66, 66), (130, 257), (301, 97)])
 def test_variant_matches_oracle(shape, flags):
     nx, ny = shape
     c = inputs.small_basin(nx, ny, seed=nx + 5 * ny, steps=80) if shape != (66, 66) else inputs.gaussian_basin_64()
+    if flags & ADVECTION:
+        c = _stirred(c, seed=nx * ny)
     n = 80
     _say(f"variant {flags} on {c.name} {nx}x{ny}")
     e, u, v, red = _gpu(c, flags, n)
@@ -58,16 +80,18 @@ def test_variant_matches_oracle(shape, flags):
     assert max(rel_l2(u, pu), rel_l2(v, pv)) > 100 * TOL  # the variant changed the answer
 
 
-@pytest.mark.parametrize("flags", [FRICTION | FILTER_UV, FILTER_UV])
+@pytest.mark.parametrize("flags", [FRICTION | FILTER_UV, FILTER_UV, ADVECTION, ADVECTION | FRICTION | FILTER_UV])
 def test_variant_is_band_height_independent(flags):
     c = inputs.small_basin(200, 173, seed=21, steps=50)
+    if flags & ADVECTION:
+        c = _stirred(c, seed=5)
     runs = [_gpu(c, flags, 50, band_rows=r) for r in (8, 16, 40)]
     for other in runs[1:]:
         for a, b in zip(runs[0][:3], other[:3]):
             assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("flags", [FRICTION, FILTER_UV, FRICTION | FILTER_UV])
+@pytest.mark.parametrize("flags", ALL_FLAGS)
 def test_variant_keeps_lake_at_rest(flags):
     c = inputs.lake_at_rest(150, 90, seed=3)
     e, u, v, _ = _gpu(c, flags, 40)
