@@ -30,7 +30,13 @@
 namespace sw2d {
 namespace {
 
-constexpr int kSorThreads = 256, kSorPlanes = 4;
+#ifndef SW2D_SOR_PLANES
+#define SW2D_SOR_PLANES 8
+#endif
+#ifndef SW2D_SOR_THREADS
+#define SW2D_SOR_THREADS 512
+#endif
+constexpr int kSorThreads = SW2D_SOR_THREADS, kSorPlanes = SW2D_SOR_PLANES;
 constexpr int kSorFoldThreads = 256;
 enum SorMode { kSorUpdate = 0, kSorResidualOnly = 1 };
 
@@ -96,31 +102,45 @@ __global__ __launch_bounds__(kSorThreads) void sor_sweep_kernel(float* __restric
     const size_t plane = (size_t)ny * w;
     double acc = 0.0;
     unsigned mx = 0u;
+    // The thread walks the planes at one position m of the other colour's array: its z
+    // neighbours are that array's values at m one plane down and up, and one of its x
+    // neighbours in a plane is the value at m itself, so each plane loads the upper z value
+    // and the outer x value only and passes the rest on.
+    const size_t o_m0 = ((size_t)k0 * ny + (row_ok ? j : 1)) * w + m;
+    float zd = 0.f, xm = 0.f;
+    if (row_ok && k0 <= nz - 2) {
+        zd = other[o_m0 - plane];
+        xm = other[o_m0];
+    }
     for (int kk = 0; kk < kSorPlanes; ++kk) {
         const int k = k0 + kk;
-        if (k > nz - 2) break;
-        // this position's cell: i = s + 2 m has the sweep's colour; its west and east
-        // neighbours sit at m - 1 + s and m + s of the other colour's row
-        const int s = (COLOR + j + k) & 1;
+        if (k > nz - 2 || !row_ok) break;
+        const size_t o = o_m0 + (size_t)kk * plane;
+        const float zu = other[o + plane];
+        const int s = (COLOR + j + k) & 1;  // i = s + 2 m has the sweep's colour
         const int i = s + 2 * m;
-        if (!row_ok || i < 1 || i > nx - 2) continue;
-        const size_t o = ((size_t)k * ny + j) * w + m;
-        const float pc = own[o];
-        const float fc = f_own[o];
-        const float sx = other[o + s] + other[o - 1 + s];
-        const float sy = other[o + w] + other[o - w];
-        const float sz = other[o + plane] + other[o - plane];
-        const float nb = fmaf(c.cz, sz, fmaf(c.cy, sy, c.cx * sx));
-        float r = 0.f;
-        if constexpr (MODE == kSorResidualOnly || COLOR == 0) r = fc - fmaf(-c.diag, pc, nb);
-        if constexpr (MODE == kSorUpdate) {
-            const float g = (nb - fc) * c.inv_diag;
-            const float pn = fmaf(c.omega, g - pc, pc);
-            own[o] = pn;
-            if constexpr (COLOR == 1) r = fc - fmaf(-c.diag, pn, nb);
+        if (i >= 1 && i <= nx - 2) {
+            const float xo = s ? other[o + 1] : other[o - 1];  // the outer x neighbour
+            const float pE = s ? xo : xm, pW = s ? xm : xo;
+            const float pc = own[o];
+            const float fc = f_own[o];
+            const float sx = pE + pW;
+            const float sy = other[o + w] + other[o - w];
+            const float sz = zu + zd;
+            const float nb = fmaf(c.cz, sz, fmaf(c.cy, sy, c.cx * sx));
+            float r = 0.f;
+            if constexpr (MODE == kSorResidualOnly || COLOR == 0) r = fc - fmaf(-c.diag, pc, nb);
+            if constexpr (MODE == kSorUpdate) {
+                const float g = (nb - fc) * c.inv_diag;
+                const float pn = fmaf(c.omega, g - pc, pc);
+                own[o] = pn;
+                if constexpr (COLOR == 1) r = fc - fmaf(-c.diag, pn, nb);
+            }
+            acc += (double)r * (double)r;
+            mx = max(mx, __float_as_uint(r) & 0x7fffffffu);
         }
-        acc += (double)r * (double)r;
-        mx = max(mx, __float_as_uint(r) & 0x7fffffffu);
+        zd = xm;
+        xm = zu;
     }
     // fixed-order tree over the workgroup
     const int t = threadIdx.x;
