@@ -318,6 +318,23 @@ int sw2d_pack_input(const float *eta, const float *u, const float *v, const floa
 int sw2d_conv3x3_fwd(const uint16_t *in, int32_t cin, const uint16_t *wk, const float *bias, int32_t relu,
                      void *out, int32_t nimg, int32_t ny, int32_t nx, void *stream);
 
+/* The first layer (cin 16, bias, ReLU) of one image reading the raw coarse state: the
+ * packing of sw2d_pack_input without noise is done while the input patch is staged, so the
+ * packed input never goes to memory (inference). Same arguments as sw2d_pack_input (mean,
+ * std: host arrays of 5) and sw2d_conv3x3_fwd; out: BF16 NHWC 32 channels. Bitwise equal to
+ * sw2d_pack_input followed by sw2d_conv3x3_fwd. */
+int sw2d_conv3x3_fwd_raw(const float *eta, const float *u, const float *v, const float *H, const uint8_t *mask,
+                         int32_t nx, int32_t ny, const float *mean, const float *std_, const uint16_t *wk,
+                         const float *bias, uint16_t *out, void *stream);
+
+/* The last layer (cin 32 -> channels 0..2 plus bias) of one image with its output added to
+ * the state as sw2d_apply_correction does (t_std: host array of 3 scales), without the
+ * output planes going to memory. Bitwise equal to sw2d_conv3x3_fwd (relu = 0) followed by
+ * sw2d_apply_correction. */
+int sw2d_conv3x3_correct(const uint16_t *in, const uint16_t *wk, const float *bias, const float *t_std,
+                         const uint8_t *mask, float *eta, float *u, float *v, int32_t nx, int32_t ny,
+                         void *stream);
+
 /* Data gradient of a layer with 32 inputs: dx[p][c] = (act_in[p][c] > 0) *
  * sum_t sum_o dy[p - off_t][o] W[t][o][c], i.e. the gradient through the convolution and
  * through the ReLU that produced the layer input act_in. dy, act_in, dx: BF16 NHWC 32

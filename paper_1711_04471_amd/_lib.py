@@ -88,6 +88,10 @@ SIGNATURES = {
     "sw2d_restrict4": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 + [_vp] * 6),
     "sw2d_pack_input": (ctypes.c_int, [_vp] * 5 + [ctypes.c_int32] * 2 +
                         [_fp, _fp, ctypes.c_float, ctypes.c_uint64, _vp, _vp]),
+    "sw2d_conv3x3_fwd_raw": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _fp, _fp,
+                                            _vp, _vp, _vp, _vp]),
+    "sw2d_conv3x3_correct": (ctypes.c_int, [_vp, _vp, _vp, _fp, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                            ctypes.c_int32, _vp]),
     "sw2d_conv3x3_fwd": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp] +
                          [ctypes.c_int32] * 3 + [_vp]),
     "sw2d_conv3x3_dgrad": (ctypes.c_int, [_vp] * 4 + [ctypes.c_int32] * 3 + [_vp]),

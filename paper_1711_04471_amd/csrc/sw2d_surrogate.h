@@ -7,7 +7,7 @@
 namespace sw2d {
 namespace sur {
 
-enum : int { kConvRelu = 0, kConvLinear3 = 1, kConvDgradMask = 2 };
+enum : int { kConvRelu = 0, kConvLinear3 = 1, kConvDgradMask = 2, kConvCorrect = 3 };
 
 struct InputNorm {
     float mean[5];
@@ -27,6 +27,28 @@ hipError_t launch_restrict4(const float* eta, const float* u, const float* v, co
 hipError_t launch_pack_input(const float* eta, const float* u, const float* v, const float* H,
                              const uint8_t* mask, int npix, const InputNorm& nrm, uint16_t* out,
                              hipStream_t s);
+// Raw state read by the first layer in place of a packed input (inference: no noise).
+struct RawIn {
+    const float* eta;
+    const float* u;
+    const float* v;
+    const float* H;
+    const uint8_t* mask;
+};
+// The last layer's output applied as the correction of the coarse state (mode kConvCorrect).
+struct CorrectOut {
+    float* eta;
+    float* u;
+    float* v;
+    const uint8_t* mask;
+    float s0, s1, s2;
+};
+// First layer (16 input channels, ReLU) with the packing of the raw state fused in.
+hipError_t launch_conv3x3_raw(const RawIn& raw, const InputNorm& nrm, const uint16_t* Wk, const float* bias,
+                              uint16_t* out_bf, int H, int W, hipStream_t s);
+// Last layer (32 -> 3, linear) whose output is added to the state as the correction.
+hipError_t launch_conv3x3_correct(const uint16_t* in, const uint16_t* Wk, const float* bias, const CorrectOut& co,
+                                  int H, int W, hipStream_t s);
 hipError_t launch_conv3x3(int kin, int mode, const uint16_t* in, const uint16_t* Wk, const float* bias,
                           uint16_t* out_bf, float* out_f, const uint16_t* relu_src, int nimg, int H, int W,
                           hipStream_t s);

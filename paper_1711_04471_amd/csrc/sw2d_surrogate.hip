@@ -96,12 +96,12 @@ __device__ __forceinline__ float splitmix_uniform(uint64_t seed, uint64_t i) {
     return (float)(z >> 40) * (1.0f / 8388608.0f) - 1.0f;
 }
 
-__global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict__ eta, const float* __restrict__ u,
-                                                         const float* __restrict__ v, const float* __restrict__ H,
-                                                         const uint8_t* __restrict__ mask, int npix, InputNorm nrm,
-                                                         uint16_t* __restrict__ out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
+// The 16 BF16 input channels of one pixel: (eta, u, v, H, mask) normalised, plus the
+// training noise on channels 0..2, then 11 zero channels; two 16 B chunks.
+__device__ __forceinline__ void pack_pixel(const float* __restrict__ eta, const float* __restrict__ u,
+                                           const float* __restrict__ v, const float* __restrict__ H,
+                                           const uint8_t* __restrict__ mask, size_t p, const InputNorm& nrm,
+                                           uint4& a, uint4& b) {
     const float x[5] = {eta[p], u[p], v[p], H[p], mask[p] ? 1.f : 0.f};
     uint16_t o[16];
 #pragma unroll
@@ -112,8 +112,6 @@ __global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict
         if (c < 3 && nrm.noise_amp > 0.f) y += nrm.noise_amp * splitmix_uniform(nrm.noise_seed, (uint64_t)p * 3 + c);
         o[c] = f2bf(y);
     }
-    uint4* dst = reinterpret_cast<uint4*>(out + (size_t)p * 16);
-    uint4 a, b;
     a.x = o[0] | ((uint32_t)o[1] << 16);
     a.y = o[2] | ((uint32_t)o[3] << 16);
     a.z = o[4] | ((uint32_t)o[5] << 16);
@@ -122,6 +120,17 @@ __global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict
     b.y = o[10] | ((uint32_t)o[11] << 16);
     b.z = o[12] | ((uint32_t)o[13] << 16);
     b.w = o[14] | ((uint32_t)o[15] << 16);
+}
+
+__global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict__ eta, const float* __restrict__ u,
+                                                         const float* __restrict__ v, const float* __restrict__ H,
+                                                         const uint8_t* __restrict__ mask, int npix, InputNorm nrm,
+                                                         uint16_t* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    uint4 a, b;
+    pack_pixel(eta, u, v, H, mask, (size_t)p, nrm, a, b);
+    uint4* dst = reinterpret_cast<uint4*>(out + (size_t)p * 16);
     dst[0] = a;
     dst[1] = b;
 }
@@ -142,14 +151,15 @@ struct ConvLds {
     static constexpr int kBytes = kRows * kCols * kStride;
 };
 
-template <int KIN, int MODE>
+template <int KIN, int MODE, bool kRaw = false>
 __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* __restrict__ in,
                                                                const uint16_t* __restrict__ Wk,
                                                                const float* __restrict__ bias,
                                                                uint16_t* __restrict__ out_bf,
                                                                float* __restrict__ out_f,
                                                                const uint16_t* __restrict__ relu_src, int H,
-                                                               int W, int nimg) {
+                                                               int W, int nimg, RawIn raw, InputNorm nrm,
+                                                               CorrectOut co) {
     using L = ConvLds<KIN>;
     __shared__ __attribute__((aligned(16))) unsigned char patch[L::kBytes];
     const int tiles_x = (W + kConvTW - 1) / kConvTW;
@@ -197,8 +207,15 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
             const int r = pix / L::kCols, c = pix - r * L::kCols;
             const int gy = y0 + r - 1, gx = x0 + c - 1;
             pre[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (e < kPatchChunks && gy >= 0 && gy < H && gx >= 0 && gx < W)
-                pre[q] = reinterpret_cast<const uint4*>(in + (img_off + (size_t)gy * W + gx) * KIN)[ch];
+            if (e < kPatchChunks && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                if constexpr (kRaw) {  // pack the raw state here (KIN = 16: chunk 0 or 1)
+                    uint4 a, b;
+                    pack_pixel(raw.eta, raw.u, raw.v, raw.H, raw.mask, img_off + (size_t)gy * W + gx, nrm, a, b);
+                    pre[q] = ch == 0 ? a : b;
+                } else {
+                    pre[q] = reinterpret_cast<const uint4*>(in + (img_off + (size_t)gy * W + gx) * KIN)[ch];
+                }
+            }
         }
     };
     auto commit = [&]() {
@@ -270,6 +287,13 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
                     w.x = o[0] | ((uint32_t)o[1] << 16);
                     w.y = o[2] | ((uint32_t)o[3] << 16);
                     *reinterpret_cast<uint2*>(out_bf + p * 32 + n0) = w;
+                }
+            } else if constexpr (MODE == kConvCorrect) {
+                // the state += activity * (output * scale), as the correction kernel does
+                if (half == 0 && co.mask[p] != 0) {
+                    co.eta[p] = fmaf(co.s0, acc[b][0] + bias[0], co.eta[p]);
+                    if (gx + 1 < W && co.mask[p + 1]) co.u[p] = fmaf(co.s1, acc[b][1] + bias[1], co.u[p]);
+                    if (gy + 1 < H && co.mask[p + W]) co.v[p] = fmaf(co.s2, acc[b][2] + bias[2], co.v[p]);
                 }
             } else {  // kConvLinear3: channels 0..2 as FP32 planes [img][3][H][W]
                 if (half == 0) {
@@ -520,9 +544,9 @@ __global__ __launch_bounds__(256) void correct_kernel(float* __restrict__ eta, f
     const bool wet = mask[p] != 0;
     if (!wet) return;
     const size_t plane = (size_t)H * W;
-    eta[p] += s0 * out[p];
-    if (x + 1 < W && mask[p + 1]) u[p] += s1 * out[plane + p];
-    if (y + 1 < H && mask[p + W]) v[p] += s2 * out[2 * plane + p];
+    eta[p] = fmaf(s0, out[p], eta[p]);
+    if (x + 1 < W && mask[p + 1]) u[p] = fmaf(s1, out[plane + p], u[p]);
+    if (y + 1 < H && mask[p + W]) v[p] = fmaf(s2, out[2 * plane + p], v[p]);
 }
 
 // ------------------------------------------------------------------------------ rmse
@@ -666,6 +690,26 @@ int resident_groups(const void* kernel, int threads) {
     return v;
 }
 
+hipError_t launch_conv3x3_raw(const RawIn& raw, const InputNorm& nrm, const uint16_t* Wk, const float* bias,
+                              uint16_t* out_bf, int H, int W, hipStream_t s) {
+    const int tiles = ((W + kConvTW - 1) / kConvTW) * ((H + kConvTH - 1) / kConvTH);
+    const int cap = resident_groups(reinterpret_cast<const void*>(&conv3x3_kernel<16, kConvRelu, true>), kConvThreads);
+    if (cap < 1) return hipErrorInvalidDeviceFunction;
+    hipLaunchKernelGGL((conv3x3_kernel<16, kConvRelu, true>), dim3(tiles < cap ? tiles : cap), dim3(kConvThreads), 0, s,
+                       nullptr, Wk, bias, out_bf, nullptr, nullptr, H, W, 1, raw, nrm, CorrectOut{});
+    return hipGetLastError();
+}
+
+hipError_t launch_conv3x3_correct(const uint16_t* in, const uint16_t* Wk, const float* bias, const CorrectOut& co,
+                                  int H, int W, hipStream_t s) {
+    const int tiles = ((W + kConvTW - 1) / kConvTW) * ((H + kConvTH - 1) / kConvTH);
+    const int cap = resident_groups(reinterpret_cast<const void*>(&conv3x3_kernel<32, kConvCorrect>), kConvThreads);
+    if (cap < 1) return hipErrorInvalidDeviceFunction;
+    hipLaunchKernelGGL((conv3x3_kernel<32, kConvCorrect>), dim3(tiles < cap ? tiles : cap), dim3(kConvThreads), 0, s,
+                       in, Wk, bias, nullptr, nullptr, nullptr, H, W, 1, RawIn{}, InputNorm{}, co);
+    return hipGetLastError();
+}
+
 hipError_t launch_conv3x3(int kin, int mode, const uint16_t* in, const uint16_t* Wk, const float* bias,
                           uint16_t* out_bf, float* out_f, const uint16_t* relu_src, int nimg, int H, int W,
                           hipStream_t s) {
@@ -679,7 +723,7 @@ hipError_t launch_conv3x3(int kin, int mode, const uint16_t* in, const uint16_t*
         if (cap < 1) return hipErrorInvalidDeviceFunction;                                            \
         const dim3 grid(tiles < cap ? tiles : cap);                                                   \
         hipLaunchKernelGGL((conv3x3_kernel<K, M>), grid, block, 0, s, in, Wk, bias, out_bf, out_f, relu_src, H, \
-                           W, nimg);                                                                  \
+                           W, nimg, RawIn{}, InputNorm{}, CorrectOut{});                              \
         return hipGetLastError();                                                                      \
     }
     SW2D_CONV_CASE(16, kConvRelu)

@@ -73,6 +73,36 @@ int sw2d_conv3x3_fwd(const uint16_t* in, int32_t cin, const uint16_t* wk, const 
                 "sw2d_conv3x3_fwd");
 }
 
+int sw2d_conv3x3_fwd_raw(const float* eta, const float* u, const float* v, const float* H, const uint8_t* mask,
+                         int32_t nx, int32_t ny, const float* mean, const float* std_, const uint16_t* wk,
+                         const float* bias, uint16_t* out, void* stream) {
+    if (!eta || !u || !v || !H || !mask || !mean || !std_ || !wk || !bias || !out || !aligned16(wk) ||
+        !aligned16(out))
+        return SW2D_EINVAL;
+    if (!dims_ok(1, ny, nx)) return SW2D_EINVAL;
+    InputNorm nrm;
+    nrm.noise_amp = 0.f;
+    nrm.noise_seed = 0;
+    for (int c = 0; c < 5; ++c) {
+        if (!(std_[c] > 0.f) || !std::isfinite(mean[c])) return SW2D_EINVAL;
+        nrm.mean[c] = mean[c];
+        nrm.inv_std[c] = 1.f / std_[c];
+    }
+    return fail(launch_conv3x3_raw(RawIn{eta, u, v, H, mask}, nrm, wk, bias, out, ny, nx,
+                                   static_cast<hipStream_t>(stream)),
+                "sw2d_conv3x3_fwd_raw");
+}
+
+int sw2d_conv3x3_correct(const uint16_t* in, const uint16_t* wk, const float* bias, const float* t_std,
+                         const uint8_t* mask, float* eta, float* u, float* v, int32_t nx, int32_t ny, void* stream) {
+    if (!in || !wk || !bias || !t_std || !mask || !eta || !u || !v || !aligned16(in) || !aligned16(wk))
+        return SW2D_EINVAL;
+    if (!dims_ok(1, ny, nx)) return SW2D_EINVAL;
+    const CorrectOut co{eta, u, v, mask, t_std[0], t_std[1], t_std[2]};
+    return fail(launch_conv3x3_correct(in, wk, bias, co, ny, nx, static_cast<hipStream_t>(stream)),
+                "sw2d_conv3x3_correct");
+}
+
 int sw2d_conv3x3_dgrad(const uint16_t* dy, const uint16_t* wd, const uint16_t* act_in, uint16_t* dx, int32_t nimg,
                        int32_t ny, int32_t nx, void* stream) {
     if (!dy || !wd || !act_in || !dx || !aligned16(dy) || !aligned16(wd) || !aligned16(dx) || !aligned16(act_in))

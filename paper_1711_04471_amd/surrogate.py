@@ -122,6 +122,25 @@ class ConvNet:
                                         n, h, w, s), "sw2d_conv3x3_fwd")
         return out
 
+    def forward_hidden_raw(self, eta, u, v, H, mask, h, w, mean_ptr, std_ptr):
+        """Layers 1-3 of one image straight from the raw coarse state (the input packing is
+        fused into layer 1). Returns layer 3's activations for ``correct``."""
+        _, acts, _, _ = self._buffers(1, h, w)
+        s = self.stream()
+        check(self.lib.sw2d_conv3x3_fwd_raw(_p(eta), _p(u), _p(v), _p(H), _p(mask), w, h, mean_ptr, std_ptr,
+                                            _p(self.wk[0]), _p(self.weight(0)[1]), _p(acts[0]), s),
+              "sw2d_conv3x3_fwd_raw")
+        for layer in (1, 2):
+            check(self.lib.sw2d_conv3x3_fwd(_p(acts[layer - 1]), 32, _p(self.wk[layer]),
+                                            _p(self.weight(layer)[1]), 1, _p(acts[layer]), 1, h, w, s),
+                  "sw2d_conv3x3_fwd")
+        return acts[2]
+
+    def correct(self, hidden, eta, u, v, mask, h, w, tstd_ptr):
+        """Layer 4 with its output added to the state as the correction (fused)."""
+        check(self.lib.sw2d_conv3x3_correct(_p(hidden), _p(self.wk[3]), _p(self.weight(3)[1]), tstd_ptr, _p(mask),
+                                            _p(eta), _p(u), _p(v), w, h, self.stream()), "sw2d_conv3x3_correct")
+
     def backward(self, x16, d_out, n, h, w, work):
         """Gradients of every layer into self.grad, for dL/dout = d_out (BF16 NHWC, 32 ch)."""
         _, acts, _, dz = self._buffers(n, h, w)
@@ -408,7 +427,6 @@ def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1
     co = Coarse(fine, case)
     s = torch.cuda.current_stream(dev).cuda_stream
     res = RolloutResult()
-    x16 = torch.empty((1, co.ny, co.nx, 16), dtype=torch.bfloat16, device=dev)
     ref = [torch.empty_like(co.eta) for _ in range(3)] + [torch.empty_like(co.H), torch.empty_like(co.mask)]
     if net is not None:
         mean_a, mp = _fptr(net.stats.in_mean)
@@ -421,15 +439,13 @@ def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1
             if net is None:
                 co.sim.step(1)
                 continue
-            # the network sees the state before the coarse step, as in training
+            # the network sees the state before the coarse step, as in training; layer 1
+            # packs the raw state itself and layer 4 adds its output to the stepped state
             e, u, v = co.sim.state()
-            check(lib.sw2d_pack_input(_p(e), _p(u), _p(v), _p(co.H), _p(co.mask), co.nx, co.ny, mp, sp,
-                                      ctypes.c_float(0.0), ctypes.c_uint64(0), _p(x16), s), "sw2d_pack_input")
-            out = net.forward(x16, 1, co.ny, co.nx)
+            hidden = net.forward_hidden_raw(e, u, v, co.H, co.mask, co.ny, co.nx, mp, sp)
             co.sim.step(1)
             e, u, v = co.sim.state()
-            check(lib.sw2d_apply_correction(_p(e), _p(u), _p(v), _p(out), _p(co.mask), co.nx, co.ny, tp, s),
-                  "sw2d_apply_correction")
+            net.correct(hidden, e, u, v, co.mask, co.ny, co.nx, tp)
         torch.cuda.synchronize(dev)
         t1 = time.perf_counter()
         fine.step(4 * judge_every)

@@ -287,3 +287,50 @@ def test_sub3_and_moments(rng):
         x = a[0][sel].astype(np.float64)
         got = res.cpu().numpy()
         np.testing.assert_allclose(got, [x.sum(), (x * x).sum()], rtol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(37, 45), (64, 96), (8, 33)])
+def test_fused_first_and_last_layers_equal_the_unfused_path(rng, shape):
+    """Layer 1 reading the raw state (packing fused in) equals pack_input + layer 1, and
+    layer 4 adding its output to the state equals layer 4 + apply_correction, bit for bit;
+    the unfused pieces are pinned to the oracle by the tests above."""
+    H, W = shape
+    fields = [rng.standard_normal((H, W)).astype(np.float32) for _ in range(4)]
+    mask = np.zeros((H, W), dtype=np.uint8)
+    mask[1:-1, 1:-1] = (rng.uniform(size=(H - 2, W - 2)) < 0.8)
+    mean = np.array([0.1, -0.2, 0.3, 20.0, 0.5], dtype=np.float32)
+    std = np.array([0.5, 0.25, 2.0, 10.0, 0.5], dtype=np.float32)
+    mp = mean.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    sp = std.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    g = [torch.as_tensor(a).to(DEV) for a in fields] + [torch.as_tensor(mask).to(DEV)]
+    W1 = torch.from_numpy(wk_layout(rng.standard_normal((32, 5, 3, 3)) * 0.3, 16).astype(np.float32)).to(DEV)
+    wk1 = torch.empty((9, 32, 16), dtype=torch.bfloat16, device=DEV)
+    check(lib().sw2d_cast_weights(ptr(W1), 16, ptr(wk1), None, stream()))
+    b1 = torch.from_numpy((rng.standard_normal(32) * 0.1).astype(np.float32)).to(DEV)
+    # unfused: pack then layer 1
+    x16 = torch.empty((H, W, 16), dtype=torch.bfloat16, device=DEV)
+    check(lib().sw2d_pack_input(*map(ptr, g), W, H, mp, sp, ctypes.c_float(0.0), ctypes.c_uint64(0), ptr(x16),
+                                stream()))
+    a1 = torch.empty((H, W, 32), dtype=torch.bfloat16, device=DEV)
+    check(lib().sw2d_conv3x3_fwd(ptr(x16), 16, ptr(wk1), ptr(b1), 1, ptr(a1), 1, H, W, stream()))
+    f1 = torch.empty_like(a1)
+    check(lib().sw2d_conv3x3_fwd_raw(*map(ptr, g), W, H, mp, sp, ptr(wk1), ptr(b1), ptr(f1), stream()))
+    torch.cuda.synchronize()
+    assert torch.equal(a1.view(torch.int16), f1.view(torch.int16))
+    # layer 4 + correction
+    W4 = torch.from_numpy(wk_layout(rng.standard_normal((3, 32, 3, 3)) * 0.1, 32).astype(np.float32)).to(DEV)
+    wk4 = torch.empty((9, 32, 32), dtype=torch.bfloat16, device=DEV)
+    check(lib().sw2d_cast_weights(ptr(W4), 32, ptr(wk4), None, stream()))
+    b4 = torch.zeros(32, dtype=torch.float32, device=DEV)
+    b4[:3] = torch.from_numpy((rng.standard_normal(3) * 0.1).astype(np.float32))
+    t_std = np.array([0.01, 0.02, 0.03], dtype=np.float32)
+    tp = t_std.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    state = [torch.as_tensor(rng.standard_normal((H, W)).astype(np.float32)).to(DEV) for _ in range(3)]
+    s2 = [t.clone() for t in state]
+    out = torch.empty((1, 3, H, W), dtype=torch.float32, device=DEV)
+    check(lib().sw2d_conv3x3_fwd(ptr(a1), 32, ptr(wk4), ptr(b4), 0, ptr(out), 1, H, W, stream()))
+    check(lib().sw2d_apply_correction(*map(ptr, state), ptr(out), ptr(g[4]), W, H, tp, stream()))
+    check(lib().sw2d_conv3x3_correct(ptr(a1), ptr(wk4), ptr(b4), tp, ptr(g[4]), *map(ptr, s2), W, H, stream()))
+    torch.cuda.synchronize()
+    for x, y in zip(state, s2):
+        assert torch.equal(x, y)
