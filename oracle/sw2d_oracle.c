@@ -35,6 +35,15 @@
  *    each derivative a one-sided difference on the upstream side of its advecting
  *    velocity, vbar the mean of the four v faces around the u face and ubar likewise,
  *    neighbours off the grid or on inactive faces counted as 0.
+ *  - wetting and drying (variant): a water cell is wet while its total depth
+ *    H + eta exceeds a threshold hmin (a choice of the caller; the datum may sit above
+ *    the still-water level, so ground that can flood is a water cell with a small or
+ *    zero total depth). A face between two water cells carries flow when both cells
+ *    are wet, or when one is wet and its surface stands higher than the other's, so
+ *    the pressure gradient pushes water into the dry cell; otherwise its predicted
+ *    velocity is 0. Every water cell takes the flux divergence; the Shapiro filter
+ *    acts on wet cells only and exchanges with wet neighbours only (a dry cell keeps
+ *    its predicted surface). Wet flags come from the old surface.
  *  - Per-step folds: V_disp = dx dy sum_wet eta', V_tot = dx dy sum_wet (H + eta'),
  *    max|u'|, max|v'|. The paper's compiler turns loop nests into maps and
  *    these reductions into folds (Sect. 4.3).
@@ -61,6 +70,27 @@ static int is_wet(const unsigned char *mask, int nx, int ny, int j, int i) {
 #define SW2D_ORACLE_FRICTION 1
 #define SW2D_ORACLE_FILTER_UV 2
 #define SW2D_ORACLE_ADVECTION 4
+#define SW2D_ORACLE_WETDRY 8
+
+/* wet/dry variant: a water cell takes part in the dynamics while its total depth
+ * exceeds hmin; land is never wet */
+static int wet_now(const double *H, const double *eta, const unsigned char *mask, int nx, int ny,
+                   int j, int i, double hmin) {
+    return is_wet(mask, nx, ny, j, i) && AT(H, j, i) + AT(eta, j, i) > hmin;
+}
+
+/* wet/dry variant: a face between cells a and b (both water) passes flow when both are
+ * wet, or when one of them is wet and its surface stands above the other's */
+static int face_open(int wa, int wb, double ea, double eb) {
+    return (wa && wb) || (wa && ea > eb) || (wb && eb > ea);
+}
+
+/* the neighbours the surface filter exchanges with: water cells, or, with wetting and
+ * drying, wet cells */
+static int filter_nb(const double *H, const double *eta, const unsigned char *mask, int nx, int ny,
+                     int j, int i, int wd, double hmin) {
+    return wd ? wet_now(H, eta, mask, nx, ny, j, i, hmin) : is_wet(mask, nx, ny, j, i);
+}
 
 /* a face value, 0 off the grid */
 static double face_at(const double *a, int nx, int ny, int j, int i) {
@@ -123,13 +153,17 @@ static void filter_faces(int nx, int ny, double e4, const unsigned char *mask, c
 
 /* One step. scratch holds 3*nx*ny doubles (Fx, Fy, es). flags: SW2D_ORACLE_FRICTION
  * (quadratic bottom friction with coefficient cd), SW2D_ORACLE_FILTER_UV,
- * SW2D_ORACLE_ADVECTION. Returns 0, or 1
- * if a water cell has non-positive total depth H + eta (the model has no drying). */
+ * SW2D_ORACLE_ADVECTION, SW2D_ORACLE_WETDRY (threshold hmin). Returns 0, or 1 if a
+ * water cell has non-positive total depth H + eta without SW2D_ORACLE_WETDRY.
+ * wd_margin, if not NULL, holds 2 doubles that are lowered to this step's smallest
+ * distance of a wet/dry decision from its threshold: [0] |H + eta - hmin| over water
+ * cells, [1] |eta_a - eta_b| over faces between a wet and a dry water cell. */
 int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, double eps,
                      const double *H, const unsigned char *mask,
                      const double *eta, const double *u, const double *v,
                      double *eta_out, double *u_out, double *v_out,
-                     double *scratch, int nthreads, int flags, double cd) {
+                     double *scratch, int nthreads, int flags, double cd, double hmin,
+                     double *wd_margin) {
     const double cx = g * dt / dx, cy = g * dt / dy;
     const double kf = dt * cd;
     const double rx = dt / dx, ry = dt / dy;
@@ -137,7 +171,9 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
     double *Fx = scratch;
     double *Fy = scratch + (size_t)nx * ny;
     double *es = scratch + 2 * (size_t)nx * ny;
+    const int wd = (flags & SW2D_ORACLE_WETDRY) != 0;
     int dry = 0;
+    double mh = INFINITY, me = INFINITY;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -145,13 +181,23 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
 #endif
 
     /* dyn, part 1: predicted face velocities; then the upwinded face fluxes. */
-#pragma omp parallel for schedule(static) reduction(| : dry)
+#pragma omp parallel for schedule(static) reduction(| : dry) reduction(min : mh, me)
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
             int w = is_wet(mask, nx, ny, j, i);
-            if (w && !(AT(H, j, i) + AT(eta, j, i) > 0.0)) dry = 1;
+            if (w && !wd && !(AT(H, j, i) + AT(eta, j, i) > 0.0)) dry = 1;
             int au = w && is_wet(mask, nx, ny, j, i + 1);
             int av = w && is_wet(mask, nx, ny, j + 1, i);
+            if (wd && w) {
+                const int d = wet_now(H, eta, mask, nx, ny, j, i, hmin);
+                const int dE = wet_now(H, eta, mask, nx, ny, j, i + 1, hmin);
+                const int dN = wet_now(H, eta, mask, nx, ny, j + 1, i, hmin);
+                mh = fmin(mh, fabs(AT(H, j, i) + AT(eta, j, i) - hmin));
+                if (au && d != dE) me = fmin(me, fabs(AT(eta, j, i) - AT(eta, j, i + 1)));
+                if (av && d != dN) me = fmin(me, fabs(AT(eta, j, i) - AT(eta, j + 1, i)));
+                au = au && face_open(d, dE, AT(eta, j, i), AT(eta, j, i + 1));
+                av = av && face_open(d, dN, AT(eta, j, i), AT(eta, j + 1, i));
+            }
             double us = 0.0, vs = 0.0, fx = 0.0, fy = 0.0;
             if (au) {
                 us = AT(u, j, i) - cx * (AT(eta, j, i + 1) - AT(eta, j, i));
@@ -204,11 +250,12 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
             if (is_wet(mask, nx, ny, j, i)) {
                 double c = AT(es, j, i);
                 double s = 0.0;
-                if (is_wet(mask, nx, ny, j, i + 1)) s += AT(es, j, i + 1) - c;
-                if (is_wet(mask, nx, ny, j, i - 1)) s += AT(es, j, i - 1) - c;
-                if (is_wet(mask, nx, ny, j + 1, i)) s += AT(es, j + 1, i) - c;
-                if (is_wet(mask, nx, ny, j - 1, i)) s += AT(es, j - 1, i) - c;
-                out = c + e4 * s;
+                if (filter_nb(H, eta, mask, nx, ny, j, i + 1, wd, hmin)) s += AT(es, j, i + 1) - c;
+                if (filter_nb(H, eta, mask, nx, ny, j, i - 1, wd, hmin)) s += AT(es, j, i - 1) - c;
+                if (filter_nb(H, eta, mask, nx, ny, j + 1, i, wd, hmin)) s += AT(es, j + 1, i) - c;
+                if (filter_nb(H, eta, mask, nx, ny, j - 1, i, wd, hmin)) s += AT(es, j - 1, i) - c;
+                /* with wetting and drying a dry cell keeps its predicted surface */
+                out = (wd && !wet_now(H, eta, mask, nx, ny, j, i, hmin)) ? c : c + e4 * s;
             }
             AT(eta_out, j, i) = out;
         }
@@ -220,6 +267,10 @@ int sw2d_oracle_step(int nx, int ny, double dx, double dy, double g, double dt, 
         filter_faces(nx, ny, e4, mask, v_out, Fy, v_face);
         memcpy(u_out, Fx, sizeof(double) * (size_t)nx * ny);
         memcpy(v_out, Fy, sizeof(double) * (size_t)nx * ny);
+    }
+    if (wd_margin) {
+        wd_margin[0] = fmin(wd_margin[0], mh);
+        wd_margin[1] = fmin(wd_margin[1], me);
     }
     return dry;
 }
@@ -259,12 +310,12 @@ void sw2d_oracle_reduce(int nx, int ny, double dx, double dy, const double *H,
 }
 
 /* nsteps steps in place on (eta, u, v). red, if not NULL, receives 4 doubles per step
- * (the folds of the state after that step). Returns 0, 1 if a water cell dried, or
- * 2 if memory ran out. */
+ * (the folds of the state after that step); wd_margin as for one step, over all steps.
+ * Returns 0, 1 if a water cell dried (without wetting and drying), or 2 if memory ran out. */
 int sw2d_oracle_run(int nx, int ny, double dx, double dy, double g, double dt, double eps,
                     const double *H, const unsigned char *mask,
                     double *eta, double *u, double *v, int nsteps, double *red, int nthreads, int flags,
-                    double cd) {
+                    double cd, double hmin, double *wd_margin) {
     size_t n = (size_t)nx * ny;
     double *buf = (double *)malloc(sizeof(double) * (6 * n + 2 * (size_t)ny));
     if (!buf) return 2;
@@ -274,7 +325,7 @@ int sw2d_oracle_run(int nx, int ny, double dx, double dy, double g, double dt, d
     int rc = 0;
     for (int s = 0; s < nsteps && rc == 0; ++s) {
         rc = sw2d_oracle_step(nx, ny, dx, dy, g, dt, eps, H, mask, ce, cu, cv, ne, nu, nv,
-                              scratch, nthreads, flags, cd);
+                              scratch, nthreads, flags, cd, hmin, wd_margin);
         if (red) sw2d_oracle_reduce(nx, ny, dx, dy, H, mask, ne, nu, nv, red + 4 * (size_t)s, rowbuf);
         double *t;
         t = ce; ce = ne; ne = t;

@@ -25,8 +25,9 @@ MUTANTS = {
     "dx_for_dy_in_v_predictor": ("vs = AT(v, j, i) - cy *", "vs = AT(v, j, i) - cx *"),
     "west_flux_index": ("double fw = i > 0 ? AT(Fx, j, i - 1) : 0.0;", "double fw = i > 0 ? AT(Fx, j, i) : 0.0;"),
     "south_flux_dropped": ("- ry * (AT(Fy, j, i) - fs)", "- ry * AT(Fy, j, i)"),
-    "shapiro_drops_north": ("if (is_wet(mask, nx, ny, j + 1, i)) s += AT(es, j + 1, i) - c;", ""),
-    "shapiro_over_land": ("if (is_wet(mask, nx, ny, j, i - 1)) s += AT(es, j, i - 1) - c;", "s += AT(es, j, i - 1) - c;"),
+    "shapiro_drops_north": ("if (filter_nb(H, eta, mask, nx, ny, j + 1, i, wd, hmin)) s += AT(es, j + 1, i) - c;", ""),
+    "shapiro_over_land": ("if (filter_nb(H, eta, mask, nx, ny, j, i - 1, wd, hmin)) s += AT(es, j, i - 1) - c;",
+                          "s += AT(es, j, i - 1) - c;"),
     "shapiro_eps_over_2": ("const double e4 = eps / 4.0;", "const double e4 = eps / 2.0;"),
     "depth_from_new_side": ("AT(H, j + 1, i) + AT(eta, j + 1, i);", "AT(H, j, i) + AT(eta, j + 1, i);"),
     "volume_counts_land": ("if (AT(mask, j, i)) {", "{"),
@@ -44,6 +45,17 @@ MUTANTS = {
     "advection_v_wrong_neighbour": ("const double by = c > 0.0 ? c * (c - face_at(v, nx, ny, j - 1, i)) / dy",
                                     "const double by = c > 0.0 ? c * (c - face_at(v, nx, ny, j, i - 1)) / dy"),
     "uv_filter_v_on_u_faces": ("filter_faces(nx, ny, e4, mask, v_out, Fy, v_face);", "filter_faces(nx, ny, e4, mask, v_out, Fy, u_face);"),
+    "wetdry_opens_toward_a_higher_dry_cell": ("return (wa && wb) || (wa && ea > eb) || (wb && eb > ea);",
+                                              "return (wa && wb) || (wa && ea < eb) || (wb && eb < ea);"),
+    "wetdry_any_wet_side_opens": ("return (wa && wb) || (wa && ea > eb) || (wb && eb > ea);", "return wa || wb;"),
+    "wetdry_two_dry_cells_open": ("return (wa && wb) || (wa && ea > eb) || (wb && eb > ea);",
+                                  "return (wa == wb) || (wa && ea > eb) || (wb && eb > ea);"),
+    "wetdry_threshold_inclusive": ("return is_wet(mask, nx, ny, j, i) && AT(H, j, i) + AT(eta, j, i) > hmin;",
+                                   "return is_wet(mask, nx, ny, j, i) && AT(H, j, i) + AT(eta, j, i) >= hmin;"),
+    "wetdry_dry_cells_filtered": ("out = (wd && !wet_now(H, eta, mask, nx, ny, j, i, hmin)) ? c : c + e4 * s;",
+                                  "out = c + e4 * s;"),
+    "wetdry_filter_across_dry_neighbours": ("return wd ? wet_now(H, eta, mask, nx, ny, j, i, hmin) : is_wet(mask, nx, ny, j, i);",
+                                            "return is_wet(mask, nx, ny, j, i);"),
 }
 
 
@@ -94,7 +106,20 @@ def _pin_variants():
     tv.test_advection_keeps_mirror_and_transpose_symmetry()
 
 
-PINS = (_pin_golden, _pin_modes, _pin_exact, _pin_volume, _pin_variants)
+def _pin_wetdry():
+    from tests import test_oracle_wetdry as tw
+    tw.test_flooding_step_by_hand()
+    tw.test_dry_cell_standing_higher_shuts_the_face()
+    tw.test_dry_cell_drained_by_its_old_velocity()
+    tw.test_filter_next_to_a_dry_cell()
+    tw.test_lake_at_rest_over_rising_ground_is_bitwise_still()
+    tw.test_equals_the_plain_step_while_every_cell_stays_wet()
+    tw.test_volume_is_conserved_through_flooding_and_drying()
+    tw.test_mirror_and_transpose_symmetry()
+    tw.test_dam_break_onto_a_dry_bed_follows_ritter()
+
+
+PINS = (_pin_golden, _pin_modes, _pin_exact, _pin_volume, _pin_variants, _pin_wetdry)
 
 
 def test_unmutated_oracle_passes_every_pin():
