@@ -68,21 +68,35 @@ enum {
  *                  velocity (u > 0: backward), vbar the mean of the four v faces around the
  *                  u face, ubar likewise; faces off the grid or inactive count as 0. Applied
  *                  before the friction division.
+ *  SW2D_WETDRY:    wetting and drying. A water cell is wet while its total depth H + eta
+ *                  exceeds hmin (the old surface decides, once per step). A face between two
+ *                  water cells carries flow when both are wet, or when one is wet and its
+ *                  surface stands above the other's (the pressure gradient pushes water into
+ *                  the dry cell); otherwise us (vs) = 0. Every water cell takes the flux
+ *                  divergence; the Shapiro filter acts on wet cells across wet neighbours only,
+ *                  and a dry cell keeps its predicted surface. H > 0 on water cells still
+ *                  holds: H is the depth below the datum, which may sit above the still-water
+ *                  level, so ground that can flood is a water cell whose surface starts at
+ *                  eta = -H (zero total depth). Taken alone (no other flag).
  * A handle with flags steps one step per pass (sw2d_set_time_blocking refuses K > 1), and
  * the batched and unfused paths take flags = 0 only. */
 #define SW2D_FRICTION 1u
 #define SW2D_FILTER_UV 2u
 #define SW2D_ADVECTION 4u
+#define SW2D_WETDRY 8u
 
 /* Grid and constants. nx, ny count every cell, land border included (>= 3 each).
  * dx, dy, dt > 0 and finite; g >= 0 and finite; eps in [0, 1] (Shapiro weight);
- * flags: 0 or a combination of SW2D_FRICTION, SW2D_FILTER_UV, SW2D_ADVECTION; cd >= 0 and finite, the
- * bottom-drag coefficient (used with SW2D_FRICTION, ignored otherwise). */
+ * flags: 0, a combination of SW2D_FRICTION, SW2D_FILTER_UV, SW2D_ADVECTION, or SW2D_WETDRY
+ * alone; cd >= 0 and finite, the bottom-drag coefficient (used with SW2D_FRICTION, ignored
+ * otherwise); hmin >= 0 and finite, the wet threshold on the total depth [m] (used with
+ * SW2D_WETDRY, ignored otherwise; the kernels compare in FP32). */
 typedef struct {
     int32_t nx, ny;
     double dx, dy, g, dt, eps;
     uint32_t flags;
     double cd;
+    double hmin;
 } sw2d_params;
 
 /* The folds of the state after one step (32 bytes; the device writes this layout). */
@@ -107,7 +121,8 @@ int32_t sw2d_ring_capacity(void);
  * ignored on land), d_mask (uint8 [ny][nx]) are read once; d_state holds 6*nx*ny
  * float32 = two (eta, u, v) buffers, buffer 0 holding the initial state; d_work is
  * the workspace. Checks (SW2D_EINVAL): sizes/constants; border cells must be land;
- * water cells need finite H > 0 and H + eta > 0; the initial state must be finite;
+ * water cells need finite H > 0 and H + eta > 0 (H + eta >= 0 with SW2D_WETDRY); the
+ * initial state must be finite;
  * the Courant number dt sqrt(g H_max) sqrt(1/dx^2 + 1/dy^2) must not exceed 1.
  * Synchronises the stream once. On success *out is a new handle. */
 int sw2d_create(const sw2d_params *p, const float *d_H, const uint8_t *d_mask, float *d_state,

@@ -20,7 +20,8 @@ SW2D_ENOSPC = -5
 class sw2d_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double),
                 ("dy", ctypes.c_double), ("g", ctypes.c_double), ("dt", ctypes.c_double),
-                ("eps", ctypes.c_double), ("flags", ctypes.c_uint32), ("cd", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("flags", ctypes.c_uint32), ("cd", ctypes.c_double),
+                ("hmin", ctypes.c_double)]
 
 
 class sw2d_red(ctypes.Structure):

@@ -63,8 +63,10 @@ bool params_ok(const sw2d_params* p) {
     if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dt)) return false;
     if (!std::isfinite(p->g) || p->g < 0.0) return false;
     if (!std::isfinite(p->eps) || p->eps < 0.0 || p->eps > 1.0) return false;
-    if (p->flags & ~(uint32_t)(SW2D_FRICTION | SW2D_FILTER_UV | SW2D_ADVECTION)) return false;
+    if (p->flags & ~(uint32_t)(SW2D_FRICTION | SW2D_FILTER_UV | SW2D_ADVECTION | SW2D_WETDRY)) return false;
+    if ((p->flags & SW2D_WETDRY) && p->flags != SW2D_WETDRY) return false;
     if (!std::isfinite(p->cd) || p->cd < 0.0) return false;
+    if (!std::isfinite(p->hmin) || p->hmin < 0.0) return false;
     return true;
 }
 
@@ -114,6 +116,7 @@ StepCoef make_coef(const sw2d_params* p) {
     k.ry = (float)(p->dt / p->dy);
     k.e4 = (float)(p->eps / 4.0);
     k.kf = (p->flags & SW2D_FRICTION) ? (float)(p->dt * p->cd) : 0.f;
+    k.hmin = (p->flags & SW2D_WETDRY) ? (float)p->hmin : 0.f;
     return k;
 }
 
@@ -233,7 +236,8 @@ int sw2d_create(const sw2d_params* p, const float* d_H, const uint8_t* d_mask, f
                                   h->stream);
     if (e == hipSuccess)
         e = launch_prep(d_H, d_mask, h->state[0][0], h->state[0][1], h->state[0][2], p->nx, p->ny,
-                        h->hp, h->flags, reinterpret_cast<double*>(h->part), h->stream);
+                        h->hp, h->flags, reinterpret_cast<double*>(h->part), h->stream,
+                        (p->flags & SW2D_WETDRY) != 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&host_flags, h->flags, sizeof host_flags, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

@@ -47,6 +47,7 @@ struct StepCoef {
     float rx, ry;  // dt / dx, dt / dy
     float e4;      // eps / 4
     float kf;      // dt cd (bottom friction; 0 without it)
+    float hmin;    // wet threshold on the total depth (wetting and drying; 0 without it)
 };
 
 // Model variants of the step (the flags of sw2d_params), as template arguments.
@@ -54,7 +55,8 @@ enum : int {
     kVarFriction = 1,
     kVarFilterUV = 2,
     kVarAdvection = 4,
-    kVarAll = kVarFriction | kVarFilterUV | kVarAdvection
+    kVarAll = kVarFriction | kVarFilterUV | kVarAdvection,
+    kVarWetDry = 8  // alone
 };
 // With advection the single-step strip keeps a 3-lane halo on its west side (the x-face
 // predictor reads u one face further west) and 2 on its east side: 59 owned columns.
@@ -110,7 +112,7 @@ hipError_t launch_unfused_step(const float* eta, const float* u, const float* v,
                                FoldPartial* part, int nparts, hipStream_t s);
 hipError_t launch_prep(const float* H, const uint8_t* mask, const float* eta, const float* u,
                        const float* v, int nx, int ny, float* hp, PrepFlags* flags,
-                       double* scratch, hipStream_t s);
+                       double* scratch, hipStream_t s, bool allow_dry = false);
 
 namespace detail {
 // Shared by the single-grid and batched C ABI (defined in sw2d_api.hip).

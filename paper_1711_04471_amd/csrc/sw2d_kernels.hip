@@ -244,14 +244,15 @@ __global__ __launch_bounds__(kFoldThreads) void sw2d_fold_kernel(const FoldParti
 }
 
 // Static preparation, once per handle: validate the inputs, pack the land mask into the
-// depth field (hp = wet ? H : 0, so wet == hp > 0) and find the deepest water cell.
+// depth field (hp = wet ? H : 0, so wet == hp > 0) and find the deepest water cell. With
+// wetting and drying (allow_dry) a water cell may start empty (H + eta = 0).
 __global__ __launch_bounds__(256) void sw2d_prep_kernel(const float* __restrict__ H,
                                                         const uint8_t* __restrict__ mask,
                                                         const float* __restrict__ eta,
                                                         const float* __restrict__ u,
                                                         const float* __restrict__ v, int nx, int ny,
                                                         float* __restrict__ hp,
-                                                        PrepFlags* __restrict__ flags) {
+                                                        PrepFlags* __restrict__ flags, bool allow_dry) {
     const size_t n = (size_t)nx * ny;
     uint32_t bad = 0;
     uint32_t hmax = 0;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(256) void sw2d_prep_kernel(const float* __restrict_
             if (!(d > 0.f) || !isfinite(d)) bad |= kBadDepth;
             else {
                 hmax = max(hmax, __float_as_uint(d));  // positive floats order like their bits
-                if (!(d + e > 0.f)) bad |= kDryCell;
+                if (allow_dry ? !(d + e >= 0.f) : !(d + e > 0.f)) bad |= kDryCell;
             }
         }
         hp[idx] = (wet && d > 0.f && isfinite(d)) ? d : 0.f;
@@ -325,6 +326,7 @@ hipError_t launch_step(int kvar, const float* eta, const float* u, const float* 
         SW2D_STEP_CASE(5)
         SW2D_STEP_CASE(6)
         SW2D_STEP_CASE(7)
+        SW2D_STEP_CASE(8)
         default:
             return hipErrorInvalidValue;
     }
@@ -365,12 +367,12 @@ hipError_t launch_fold(const FoldPartial* part, int nparts, int stride, int nste
 
 hipError_t launch_prep(const float* H, const uint8_t* mask, const float* eta, const float* u,
                        const float* v, int nx, int ny, float* hp, PrepFlags* flags,
-                       double* scratch, hipStream_t s) {
+                       double* scratch, hipStream_t s, bool allow_dry) {
     const size_t n = (size_t)nx * ny;
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(sw2d_prep_kernel, dim3((unsigned)blocks), dim3(256), 0, s, H, mask, eta, u, v,
-                       nx, ny, hp, flags);
+                       nx, ny, hp, flags, allow_dry);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int G = ny < kHsumBlocks ? ny : kHsumBlocks;

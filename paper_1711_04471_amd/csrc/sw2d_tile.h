@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sw2d_internal.h"
 
 namespace sw2d {
@@ -64,7 +66,14 @@ __device__ __forceinline__ void store(float* p, float x) {
 struct RowX {
     float e, h, pe, us;
     bool w, wE, wW, au;
+    bool d, dE, dW;  // wetting and drying: wet now (total depth above the threshold)
 };
+
+// Wetting and drying: a face between two water cells a and b carries flow when both are
+// wet, or when one is wet and its surface stands above the other's.
+__device__ __forceinline__ bool face_open(bool da, bool db, float ea, float eb) {
+    return (da && db) || (da && ea > eb) || (db && eb > ea);
+}
 
 // Quadratic bottom friction (variant): the predictor divided by 1 + dt cd |u_old| / h_face,
 // h_face the mean total depth of the face's two cells.
@@ -90,7 +99,16 @@ __device__ __forceinline__ RowX row_x(float e, float hpr, float ur, const StepCo
     o.wW = hpW > 0.f;
     const bool au = o.w && o.wE;
     o.au = au;
-    o.us = au ? fmaf(-k.cx, eE - e, ur) : 0.f;
+    if constexpr ((kVar & kVarWetDry) != 0) {
+        // every lane takes the exchange before any select
+        const float hW = from_west(o.h);
+        o.d = o.h > k.hmin;
+        o.dE = hpE + eE > k.hmin;
+        o.dW = hW > k.hmin;
+        o.us = (au && face_open(o.d, o.dE, e, eE)) ? fmaf(-k.cx, eE - e, ur) : 0.f;
+    } else {
+        o.us = au ? fmaf(-k.cx, eE - e, ur) : 0.f;
+    }
     if constexpr ((kVar & kVarFriction) != 0) o.us = au ? friction(o.us, ur, o.h, hpE + eE, k) : 0.f;
     // an inactive face has us = 0, so its flux is 0 without a second select
     const float fx = o.us * (o.us > 0.f ? o.h : hpE + eE);
@@ -106,7 +124,11 @@ __device__ __forceinline__ void face_y(float v_lo, float e_lo, float h_lo, bool 
                                        bool& av) {
 #pragma clang fp contract(off)
     av = w_lo && w_hi;
-    vs = av ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
+    if constexpr ((kVar & kVarWetDry) != 0) {
+        vs = (av && face_open(h_lo > k.hmin, h_hi > k.hmin, e_lo, e_hi)) ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
+    } else {
+        vs = av ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
+    }
     if constexpr ((kVar & kVarFriction) != 0) vs = av ? friction(vs, v_lo, h_lo, h_hi, k) : 0.f;
     fy = vs * (vs > 0.f ? h_lo : h_hi);  // vs = 0 on an inactive face
 }
@@ -123,6 +145,20 @@ __device__ __forceinline__ float shapiro(float es_c, bool w_c, bool wE, bool wW,
     if (w_n) s += es_n - es_c;
     if (w_s) s += es_s - es_c;
     return w_c ? fmaf(e4, s, es_c) : 0.f;
+}
+
+// Wetting and drying: the filter acts on wet cells (d_c) across wet neighbours; a dry
+// cell keeps its predicted surface (0 on land, where es is 0).
+__device__ __forceinline__ float shapiro_wd(float es_c, bool d_c, bool dE, bool dW, float es_n, bool d_n,
+                                            float es_s, bool d_s, float e4) {
+#pragma clang fp contract(off)
+    const float esE = from_east(es_c);
+    const float esW = from_west(es_c);
+    float s = dE ? esE - es_c : 0.f;
+    if (dW) s += esW - es_c;
+    if (d_n) s += es_n - es_c;
+    if (d_s) s += es_s - es_c;
+    return d_c ? fmaf(e4, s, es_c) : es_c;
 }
 
 // The same filter on face velocities (variant): c on an active face, neighbours east and
@@ -145,9 +181,17 @@ __device__ __forceinline__ float shapiro_face(float c, bool act, float n_val, bo
 // predictor, flux and partial surface update; row r-1 (r+1 marching south) its y-face and
 // the predicted surface es; row r-2 (r+2) the Shapiro filter. Every output value is the
 // same expression in either direction.
+// Wet flags of the old surface for rows 1, 2 and 3 behind (wetting and drying only; an
+// empty base otherwise, so the other pipelines carry no unused state).
+struct StageWetFlags {
+    bool d1 = false, dE1 = false, dW1 = false, d2 = false, dE2 = false, dW2 = false, d3 = false;
+};
+struct StageNoFlags {};
+
 template <bool kNorth, int kVar = 0>
-struct Stage {
+struct Stage : std::conditional_t<(kVar & kVarWetDry) != 0, StageWetFlags, StageNoFlags> {
     static constexpr bool kFilterUV = (kVar & kVarFilterUV) != 0;
+    static constexpr bool kWetDry = (kVar & kVarWetDry) != 0;
     // rows 1, 2 and 3 behind the one being consumed (in march order)
     float e1 = 0.f, h1 = 0.f, hp1 = 0.f, v1 = 0.f, pe1 = 0.f, us1 = 0.f, fy1 = 0.f, vs1 = 0.f;
     bool w1 = false, wE1 = false, wW1 = false;
@@ -168,7 +212,8 @@ struct Stage {
             bool av;
             face_y<kVar>(v1, e1, h1, w1, X.e, X.h, X.w, k, vs, fy, av);
             const float es = w1 ? fmaf(-k.ry, fy - fy2, pe1) : 0.f;
-            eta_o = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
+            if constexpr (kWetDry) eta_o = shapiro_wd(es2, this->d2, this->dE2, this->dW2, es, this->d1, es3, this->d3, k.e4);
+            else eta_o = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
             if constexpr (kFilterUV) {
                 // north neighbour: row r-1 (u) and the face r-1|r (v); south: row r-3, face r-3|r-2
                 u_o = shapiro_face(us2, au2, us1, au1, us3, au3, k.e4);
@@ -195,7 +240,8 @@ struct Stage {
             bool av;
             face_y<kVar>(vr, X.e, X.h, X.w, e1, h1, w1, k, vs, fy, av);
             const float es = w1 ? fmaf(-k.ry, fy1 - fy, pe1) : 0.f;
-            eta_o = shapiro(es2, w2, wE2, wW2, es3, w3, es, w1, k.e4);
+            if constexpr (kWetDry) eta_o = shapiro_wd(es2, this->d2, this->dE2, this->dW2, es3, this->d3, es, this->d1, k.e4);
+            else eta_o = shapiro(es2, w2, wE2, wW2, es3, w3, es, w1, k.e4);
             if constexpr (kFilterUV) {
                 // north neighbour: row r+3 (u) and the face r+3|r+4 (v); south: row r+1, face r+1|r+2
                 u_o = shapiro_face(us2, au2, us3, au3, us1, au1, k.e4);
@@ -221,6 +267,15 @@ struct Stage {
         if constexpr (kFilterUV) {
             au2 = au1;
             au1 = X.au;
+        }
+        if constexpr (kWetDry) {
+            this->d3 = this->d2;
+            this->d2 = this->d1;
+            this->dE2 = this->dE1;
+            this->dW2 = this->dW1;
+            this->d1 = X.d;
+            this->dE1 = X.dE;
+            this->dW1 = X.dW;
         }
         us2 = us1;
         hp2 = hp1;

@@ -213,6 +213,31 @@ def ensemble(n: int = 256, seed: int = 4, steps: int = 1000, sizes=None) -> list
     return [ensemble_member(k, nx, ny, steps) for k, (nx, ny) in enumerate(sizes)]
 
 
+def shore_basin(nx: int, ny: int, seed: int, steps: int = 60, dx: float = 500.0, level: float = -1.0,
+                n_bumps: int = 3, eps: float = 0.05) -> Case:
+    """A basin with a beach, for wetting and drying: the seeded basin's depth (5..50 m below
+    the datum) ramps down east of x = 0.6 nx to 0.2 m at x = 0.95 nx and stays there; the
+    still water stands at ``level`` (below the datum), so ground shallower than -level is
+    dry at rest with its surface on the ground (eta = -H). Bumps of 0.5..2 m are added on
+    the cells that are under water at rest."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H64 = bathymetry(rng, nx, ny)
+    mask = land_mask(rng, nx, ny)
+    bumps = gaussian_bumps(rng, nx, ny, n_bumps, a_range=(0.5, 2.0))
+    x = (np.arange(nx) + 0.5) / nx
+    ramp = np.clip((0.95 - x) / 0.35, 0.0, 1.0)[None, :]
+    H64 = 0.2 + (H64 - 0.2) * ramp
+    under = (mask != 0) & (H64 + level > 0.0)
+    eta64 = np.where(under, level + bumps, -H64)
+    H = H64.astype(np.float32)
+    eta = np.where(mask != 0, eta64, 0.0).astype(np.float32)
+    h_max = float(H[mask != 0].max())
+    dt = stable_dt(dx, dx, G, h_max)
+    z = np.zeros((ny, nx), dtype=np.float32)
+    return Case(f"shore_{nx}x{ny}_s{seed}", nx, ny, dx, dx, G, dt, eps, H, mask, eta, z, z.copy(), steps,
+                meta={"seed": seed, "n_bumps": n_bumps, "level": level})
+
+
 def lake_at_rest(nx: int, ny: int, seed: int, level: float = 0.25) -> Case:
     """Random depth and mask with a flat surface at ``level`` on wet cells and no flow."""
     c = seeded_basin(f"rest_{nx}x{ny}_s{seed}", nx, ny, 500.0, seed=seed, n_bumps=0, steps=20)

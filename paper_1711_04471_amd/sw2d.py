@@ -18,11 +18,12 @@ RED_DTYPE = np.dtype([("step", np.int64), ("vol_total", np.float64), ("vol_disp"
 FRICTION = 1   # quadratic bottom friction on the predictor (coefficient cd)
 FILTER_UV = 2  # the Shapiro filter on the predicted velocities as well
 ADVECTION = 4  # first-order upwind momentum advection in the predictor
+WETDRY = 8     # wetting and drying with a total-depth threshold hmin (alone)
 
 
-def params(nx, ny, dx, dy, g, dt, eps, flags=0, cd=0.0) -> sw2d_params:
+def params(nx, ny, dx, dy, g, dt, eps, flags=0, cd=0.0, hmin=0.0) -> sw2d_params:
     return sw2d_params(int(nx), int(ny), float(dx), float(dy), float(g), float(dt), float(eps),
-                       int(flags), float(cd))
+                       int(flags), float(cd), float(hmin))
 
 
 def workspace_bytes(p: sw2d_params) -> int:
@@ -48,13 +49,14 @@ class Sw2d:
     shape [ny][nx]). Device buffers are torch tensors owned by this object.
     """
 
-    def __init__(self, nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, device="cuda", flags=0, cd=0.0):
+    def __init__(self, nx, ny, dx, dy, g, dt, eps, H, mask, eta, u, v, device="cuda", flags=0, cd=0.0,
+                 hmin=0.0):
         lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("Sw2d runs on a GPU device only")
         self.nx, self.ny = int(nx), int(ny)
-        self.p = params(nx, ny, dx, dy, g, dt, eps, flags, cd)
+        self.p = params(nx, ny, dx, dy, g, dt, eps, flags, cd, hmin)
         n = self.nx * self.ny
         self.H = _dev_tensor(H, torch.float32, self.device)
         self.mask = _dev_tensor(mask, torch.uint8, self.device)
@@ -73,9 +75,9 @@ class Sw2d:
         self.h = h
 
     @classmethod
-    def from_case(cls, case, device="cuda", flags=0, cd=0.0):
+    def from_case(cls, case, device="cuda", flags=0, cd=0.0, hmin=0.0):
         return cls(case.nx, case.ny, case.dx, case.dy, case.g, case.dt, case.eps, case.H,
-                   case.mask, case.eta, case.u, case.v, device=device, flags=flags, cd=cd)
+                   case.mask, case.eta, case.u, case.v, device=device, flags=flags, cd=cd, hmin=hmin)
 
     def _handle(self):
         if self.h is None:

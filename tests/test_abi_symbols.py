@@ -53,6 +53,24 @@ def test_host_only_calls(lib):
     assert L.sw2d_step(None, 1) == _lib.SW2D_ESTATE
 
 
+def test_variant_flags_are_checked_on_the_host(lib):
+    """Wetting and drying is taken alone with a finite hmin >= 0; unknown flags are refused."""
+    from paper_1711_04471_amd import _lib
+    from paper_1711_04471_amd.sw2d import ADVECTION, FILTER_UV, FRICTION, WETDRY, params
+    L = _lib.load()
+
+    def ws(**kw):
+        return L.sw2d_workspace_bytes(ctypes.byref(params(66, 66, 100.0, 100.0, 9.81, 5.0, 0.05, **kw)))
+
+    assert ws(flags=WETDRY, hmin=0.05) > 0 and ws(flags=WETDRY, hmin=0.0) > 0
+    assert ws(flags=FRICTION | FILTER_UV | ADVECTION, cd=0.002) > 0
+    for flags in (WETDRY | FRICTION, WETDRY | FILTER_UV, WETDRY | ADVECTION, 16):
+        assert ws(flags=flags) == 0, flags
+    for hmin in (-0.01, float("nan"), float("inf")):
+        assert ws(flags=WETDRY, hmin=hmin) == 0
+    assert ws(flags=FRICTION, cd=-1.0) == 0
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_1711_04471_amd import _lib
     monkeypatch.setattr(_lib, "_lib", None)
