@@ -96,7 +96,7 @@ SURROGATE_PASS = (3, 32)
 
 
 def kernel_name(spp):
-    return "sw2d_step_kernel" if spp == 1 else f"sw2d_stepk_kernel<{spp}>"
+    return "sw2d_step_kernel<0>" if spp == 1 else f"sw2d_stepk_kernel<{spp}>"
 
 
 def counter_record(spp):
