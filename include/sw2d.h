@@ -342,6 +342,28 @@ int sw2d_conv3x3_fwd_raw(const float *eta, const float *u, const float *v, const
                          int32_t nx, int32_t ny, const float *mean, const float *std_, const uint16_t *wk,
                          const float *bias, uint16_t *out, void *stream);
 
+/* The whole network on one image in one pass (inference): the packing of the raw coarse
+ * state, layers 1-3 (bias, ReLU) and layer 4 (channels 0..2 plus bias), with the
+ * intermediate maps kept in on-chip memory. eta, u, v, H, mask, nx, ny, mean, std_: as
+ * sw2d_conv3x3_fwd_raw; wk, bias: host arrays of 4 device pointers, wk[0] BF16 [9][32][16],
+ * wk[1..3] BF16 [9][32][32], bias[l] FP32 [32], all 16 B aligned; out: FP32 planes
+ * [3][ny][nx] (device). Bitwise equal to sw2d_pack_input (no noise), three sw2d_conv3x3_fwd
+ * with relu = 1 and one with relu = 0. */
+int sw2d_cnn_forward(const float *eta, const float *u, const float *v, const float *H, const uint8_t *mask,
+                     int32_t nx, int32_t ny, const float *mean, const float *std_, const uint16_t *const *wk,
+                     const float *const *bias, float *out, void *stream);
+
+/* nsteps corrected coarse steps of the surrogate on a coarse-grid handle, all enqueued on the
+ * handle's stream without host synchronisation: each step runs sw2d_cnn_forward on the
+ * current state into delta (FP32 planes [3][ny][nx], device scratch of the caller), advances
+ * the handle one step (sw2d_step) and adds the network's output to the new state as
+ * sw2d_apply_correction does (t_std: host array of 3 scales). H, mask: the coarse grid's
+ * depth and water mask (device); mean, std_, wk, bias: as sw2d_cnn_forward. The network sees
+ * the state before the step and its output corrects the state after it. */
+int sw2d_surrogate_advance(sw2d_t coarse, int32_t nsteps, const float *H, const uint8_t *mask, const float *mean,
+                           const float *std_, const uint16_t *const *wk, const float *const *bias,
+                           const float *t_std, float *delta);
+
 /* The last layer (cin 32 -> channels 0..2 plus bias) of one image with its output added to
  * the state as sw2d_apply_correction does (t_std: host array of 3 scales), without the
  * output planes going to memory. Bitwise equal to sw2d_conv3x3_fwd (relu = 0) followed by

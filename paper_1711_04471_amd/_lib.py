@@ -91,6 +91,10 @@ SIGNATURES = {
                         [_fp, _fp, ctypes.c_float, ctypes.c_uint64, _vp, _vp]),
     "sw2d_conv3x3_fwd_raw": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _fp, _fp,
                                             _vp, _vp, _vp, _vp]),
+    "sw2d_cnn_forward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _fp, _fp,
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _vp, _vp]),
+    "sw2d_surrogate_advance": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _fp, _fp, ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.POINTER(ctypes.c_void_p), _fp, _vp]),
     "sw2d_conv3x3_correct": (ctypes.c_int, [_vp, _vp, _vp, _fp, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                             ctypes.c_int32, _vp]),
     "sw2d_conv3x3_fwd": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp] +

@@ -188,6 +188,13 @@ namespace detail {
 bool params_valid(const sw2d_params* p) { return params_ok(p); }
 StepCoef make_coef(const sw2d_params* p) { return ::make_coef(p); }
 void set_hip_message(const char* msg) { std::snprintf(g_hip_msg, sizeof g_hip_msg, "%s", msg); }
+bool handle_info(sw2d_t h, hipStream_t* stream, int* nx, int* ny) {
+    if (!h) return false;
+    *stream = h->stream;
+    *nx = h->p.nx;
+    *ny = h->p.ny;
+    return true;
+}
 }  // namespace detail
 }  // namespace sw2d
 

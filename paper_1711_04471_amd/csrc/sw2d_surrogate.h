@@ -49,6 +49,13 @@ hipError_t launch_conv3x3_raw(const RawIn& raw, const InputNorm& nrm, const uint
 // Last layer (32 -> 3, linear) whose output is added to the state as the correction.
 hipError_t launch_conv3x3_correct(const uint16_t* in, const uint16_t* Wk, const float* bias, const CorrectOut& co,
                                   int H, int W, hipStream_t s);
+// The four layers of one image in one pass, the maps kept on chip (inference).
+struct FusedNet {
+    const uint16_t* wk[4];  // BF16 [9][32][cin], cin = 16, 32, 32, 32
+    const float* bias[4];   // [32]
+};
+hipError_t launch_cnn_fused(const RawIn& raw, const InputNorm& nrm, const FusedNet& net, float* out_f, int H,
+                            int W, hipStream_t s);
 hipError_t launch_conv3x3(int kin, int mode, const uint16_t* in, const uint16_t* Wk, const float* bias,
                           uint16_t* out_bf, float* out_f, const uint16_t* relu_src, int nimg, int H, int W,
                           hipStream_t s);

@@ -34,11 +34,15 @@ namespace sur {
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    // round to nearest even (finite inputs)
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even (one hardware conversion).
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// Two values to BF16, packed with a in the low half.
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -96,13 +100,11 @@ __device__ __forceinline__ float splitmix_uniform(uint64_t seed, uint64_t i) {
     return (float)(z >> 40) * (1.0f / 8388608.0f) - 1.0f;
 }
 
-// The 16 BF16 input channels of one pixel: (eta, u, v, H, mask) normalised, plus the
-// training noise on channels 0..2, then 11 zero channels; two 16 B chunks.
-__device__ __forceinline__ void pack_pixel(const float* __restrict__ eta, const float* __restrict__ u,
-                                           const float* __restrict__ v, const float* __restrict__ H,
-                                           const uint8_t* __restrict__ mask, size_t p, const InputNorm& nrm,
-                                           uint4& a, uint4& b) {
-    const float x[5] = {eta[p], u[p], v[p], H[p], mask[p] ? 1.f : 0.f};
+// The 16 BF16 input channels of one pixel from its raw values x = (eta, u, v, H, mask):
+// normalised, plus the training noise on channels 0..2, then 11 zero channels; two 16 B
+// chunks. p is the pixel's index (the noise counter).
+__device__ __forceinline__ void pack_values(const float (&x)[5], size_t p, const InputNorm& nrm, uint4& a,
+                                            uint4& b) {
     uint16_t o[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) o[c] = 0;
@@ -120,6 +122,14 @@ __device__ __forceinline__ void pack_pixel(const float* __restrict__ eta, const 
     b.y = o[10] | ((uint32_t)o[11] << 16);
     b.z = o[12] | ((uint32_t)o[13] << 16);
     b.w = o[14] | ((uint32_t)o[15] << 16);
+}
+
+__device__ __forceinline__ void pack_pixel(const float* __restrict__ eta, const float* __restrict__ u,
+                                           const float* __restrict__ v, const float* __restrict__ H,
+                                           const uint8_t* __restrict__ mask, size_t p, const InputNorm& nrm,
+                                           uint4& a, uint4& b) {
+    const float x[5] = {eta[p], u[p], v[p], H[p], mask[p] ? 1.f : 0.f};
+    pack_values(x, p, nrm, a, b);
 }
 
 __global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict__ eta, const float* __restrict__ u,
@@ -180,13 +190,12 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
 #pragma unroll
         for (int kc = 0; kc < kK; ++kc)
             a[t][kc] = *reinterpret_cast<const bf16x8*>(Wk + ((size_t)t * 32 + j) * KIN + kc * 16 + half * 8);
-    float bv4[4][4];
-    if constexpr (MODE == kConvRelu) {
+    // the bias is the accumulators' initial value (lane: output channels 8 q + 4 half + e)
+    f32x16 binit;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) bv4[q][e] = bias[8 * q + 4 * half + e];
-    }
+        for (int e = 0; e < 4; ++e) binit[4 * q + e] = MODE == kConvDgradMask ? 0.f : bias[8 * q + 4 * half + e];
 
     // The next tile's input patch is fetched into registers while the current one is
     // multiplied, then written to LDS: every load of a patch is in flight at once.
@@ -242,9 +251,7 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
 
         f32x16 acc[kConvRowsPerWave];
 #pragma unroll
-        for (int b = 0; b < kConvRowsPerWave; ++b)
-#pragma unroll
-            for (int t = 0; t < 16; ++t) acc[b][t] = 0.f;
+        for (int b = 0; b < kConvRowsPerWave; ++b) acc[b] = binit;
 
 #pragma unroll
         for (int b = 0; b < kConvRowsPerWave; ++b) {
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
                     uint16_t o[4];
                     if constexpr (MODE == kConvRelu) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) o[e] = f2bf(fmaxf(acc[b][4 * q + e] + bv4[q][e], 0.f));
+                        for (int e = 0; e < 4; ++e) o[e] = f2bf(fmaxf(acc[b][4 * q + e], 0.f));
                     } else {
                         const uint2 m = *reinterpret_cast<const uint2*>(relu_src + p * 32 + n0);
                         const uint16_t mv[4] = {(uint16_t)(m.x & 0xffff), (uint16_t)(m.x >> 16),
@@ -291,18 +298,231 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* _
             } else if constexpr (MODE == kConvCorrect) {
                 // the state += activity * (output * scale), as the correction kernel does
                 if (half == 0 && co.mask[p] != 0) {
-                    co.eta[p] = fmaf(co.s0, acc[b][0] + bias[0], co.eta[p]);
-                    if (gx + 1 < W && co.mask[p + 1]) co.u[p] = fmaf(co.s1, acc[b][1] + bias[1], co.u[p]);
-                    if (gy + 1 < H && co.mask[p + W]) co.v[p] = fmaf(co.s2, acc[b][2] + bias[2], co.v[p]);
+                    co.eta[p] = fmaf(co.s0, acc[b][0], co.eta[p]);
+                    if (gx + 1 < W && co.mask[p + 1]) co.u[p] = fmaf(co.s1, acc[b][1], co.u[p]);
+                    if (gy + 1 < H && co.mask[p + W]) co.v[p] = fmaf(co.s2, acc[b][2], co.v[p]);
                 }
             } else {  // kConvLinear3: channels 0..2 as FP32 planes [img][3][H][W]
                 if (half == 0) {
 #pragma unroll
                     for (int e = 0; e < 3; ++e)
-                        out_f[((size_t)img * 3 + e) * H * W + (size_t)gy * W + gx] = acc[b][e] + bias[e];
+                        out_f[((size_t)img * 3 + e) * H * W + (size_t)gy * W + gx] = acc[b][e];
                 }
             }
         }
+    }
+}
+
+// ------------------------------------------------------------------------------ fused forward
+// The four layers of one image in one pass (inference). A workgroup owns a kFuTH x kFuTW tile
+// of output pixels and computes every layer over the tile grown by the receptive field still
+// ahead of it: layer 1 over (TH + 6) x (TW + 6) pixels of the (TH + 8) x (TW + 8) packed input,
+// layer 2 over (TH + 4) x (TW + 4), layer 3 over (TH + 2) x (TW + 2), layer 4 over the tile.
+// The maps stay in LDS, two buffers used in turn; a map's pixels outside the image are stored
+// as 0, which is the next layer's zero padding. A layer's pixels are taken 32 at a time in
+// row-major order of its region (the lane's address carries the row wrap), so the MFMA blocks
+// do not depend on the region's width. Taps, channel chunks, the packing of the input and the
+// epilogues are those of the layer-by-layer kernels: the output is bitwise theirs.
+constexpr int kFuTH = 16;
+constexpr int kFuTW = 32;
+constexpr int kFuThreads = 512;
+constexpr int kFuWaves = kFuThreads / 64;
+
+template <int L>  // the region of layer L's output; L = 0 is the packed input
+struct FuRegion {
+    static constexpr int kHalo = 4 - L;
+    static constexpr int kRows = kFuTH + 2 * kHalo;
+    static constexpr int kCols = kFuTW + 2 * kHalo;
+    static constexpr int kPix = kRows * kCols;
+    static constexpr int kStride = (L == 0 ? 32 : 64) + 16;  // bytes per pixel, 16 B aligned, spreads banks
+    static constexpr int kBytes = kPix * kStride;
+};
+// buffer A holds layer 1's map, then layer 3's; buffer B the packed input, then layer 2's map
+constexpr int kFuBufA = FuRegion<1>::kBytes;
+constexpr int kFuBufB = FuRegion<0>::kBytes > FuRegion<2>::kBytes ? FuRegion<0>::kBytes : FuRegion<2>::kBytes;
+static_assert(FuRegion<3>::kBytes <= kFuBufA, "layer 3 map in buffer A");
+constexpr int kFuWSlot = 9 * 32 * 32 * 2;  // one layer's BF16 weights (the widest)
+constexpr int kFuBiasBytes = 4 * 32 * 4;
+constexpr int kFuLds = kFuBufA + kFuBufB + 2 * kFuWSlot + kFuBiasBytes;
+constexpr int kFuWPer = (kFuWSlot / 16 + kFuThreads - 1) / kFuThreads;  // 16 B weight chunks per thread
+constexpr int kFuRawPer = (FuRegion<0>::kPix + kFuThreads - 1) / kFuThreads;  // input pixels per thread
+
+// The bias pattern of a lane (output channels 8 q + 4 half + e) as an accumulator value.
+__device__ __forceinline__ f32x16 bias_pattern(const float* __restrict__ bias, int half) {
+    f32x16 b;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) b[4 * q + e] = bias[8 * q + 4 * half + e];
+    return b;
+}
+
+// One layer over its region: input map in_lds (region L - 1), output map out_lds (region L),
+// or, for the last layer, channels 0..2 to the FP32 planes out_f [3][H][W]. bias: the layer's
+// 32 biases in LDS; a lane's output channels start from theirs. A block's B
+// operands (all taps and channel chunks) are read from LDS before its first product, so the
+// reads overlap the products instead of waiting one by one.
+template <int L, int KIN, bool kLast>
+__device__ __forceinline__ void fused_layer(const unsigned char* __restrict__ in_lds, unsigned char* __restrict__ out_lds,
+                                            const bf16x8 (&a)[9][2], const float* __restrict__ bias, float* __restrict__ out_f,
+                                            int y0, int x0, int H, int W, int wave, int half, int j) {
+    using In = FuRegion<L - 1>;
+    using Out = FuRegion<L>;
+    constexpr int kK = KIN / 16;
+    constexpr int kBlocks = (Out::kPix + 31) / 32;
+    const int oy = y0 - Out::kHalo, ox = x0 - Out::kHalo;  // image coordinates of the region's first pixel
+    for (int blk = wave; blk < kBlocks; blk += kFuWaves) {
+        const int P = blk * 32 + j;
+        const bool valid = P < Out::kPix;
+        const int Pc = valid ? P : Out::kPix - 1;  // the last block's spare lanes read a real pixel
+        const int ry = Pc / Out::kCols, rx = Pc - ry * Out::kCols;
+        const unsigned char* base = in_lds + (ry * In::kCols + rx) * In::kStride + half * 16;
+        bf16x8 bv[9][kK];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t - 3 * (t / 3);
+#pragma unroll
+            for (int kc = 0; kc < kK; ++kc)
+                bv[t][kc] = *reinterpret_cast<const bf16x8*>(base + (ky * In::kCols + kx) * In::kStride + kc * 32);
+        }
+        f32x16 acc = bias_pattern(bias, half);
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int kc = 0; kc < kK; ++kc) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t][kc], bv[t][kc], acc, 0, 0, 0);
+        // the scheduler is told to issue the block's LDS reads before its products
+        __builtin_amdgcn_sched_group_barrier(0x100, 9 * kK, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 9 * kK, 0);
+        const int gy = oy + ry, gx = ox + rx;
+        const bool inside = valid && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        if constexpr (!kLast) {
+            // lane holds pixel P, output channels n = 8 q + 4 half + (0..3)
+            if (valid) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int n0 = 8 * q + 4 * half;
+                    uint2 w;
+                    w.x = f2bf2(fmaxf(acc[4 * q + 0], 0.f), fmaxf(acc[4 * q + 1], 0.f));
+                    w.y = f2bf2(fmaxf(acc[4 * q + 2], 0.f), fmaxf(acc[4 * q + 3], 0.f));
+                    if (!inside) w = make_uint2(0u, 0u);
+                    *reinterpret_cast<uint2*>(out_lds + P * Out::kStride + n0 * 2) = w;
+                }
+            }
+        } else {
+            if (inside && half == 0) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) out_f[(size_t)e * H * W + (size_t)gy * W + gx] = acc[e];
+            }
+        }
+    }
+}
+
+// A operands of one layer (lane: output channel j, channels 8 half.. of each 16-chunk) from
+// the layer's weights staged in LDS ([9][32][KIN] BF16).
+template <int KIN>
+__device__ __forceinline__ void fused_weights(bf16x8 (&a)[9][2], const unsigned char* __restrict__ slot, int half, int j) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int kc = 0; kc < KIN / 16; ++kc)
+            a[t][kc] = *reinterpret_cast<const bf16x8*>(slot + (((t * 32 + j) * KIN) + kc * 16 + half * 8) * 2);
+}
+
+__global__ __launch_bounds__(kFuThreads) void cnn_fused_kernel(RawIn raw, InputNorm nrm, FusedNet net,
+                                                               float* __restrict__ out_f, int H, int W) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[kFuLds];
+    unsigned char* bufA = lds;
+    unsigned char* bufB = lds + kFuBufA;
+    unsigned char* wslot[2] = {lds + kFuBufA + kFuBufB, lds + kFuBufA + kFuBufB + kFuWSlot};
+    float* bias_lds = reinterpret_cast<float*>(lds + kFuBufA + kFuBufB + 2 * kFuWSlot);
+    const int tiles_x = (W + kFuTW - 1) / kFuTW;
+    const int total = tiles_x * ((H + kFuTH - 1) / kFuTH);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int half = lane / 32, j = lane % 32;
+    if (threadIdx.x < 128) bias_lds[threadIdx.x] = net.bias[threadIdx.x / 32][threadIdx.x % 32];
+
+    // the packed input of a tile: raw values fetched into registers, packed into buffer B
+    float rx_[kFuRawPer][5];
+    bool rin[kFuRawPer];
+    auto fetch = [&](int tile) {
+        const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        const int y0 = ty * kFuTH - FuRegion<0>::kHalo, x0 = tx * kFuTW - FuRegion<0>::kHalo;
+#pragma unroll
+        for (int q = 0; q < kFuRawPer; ++q) {
+            const int e = threadIdx.x + q * kFuThreads;
+            const int r = e / FuRegion<0>::kCols, c = e - r * FuRegion<0>::kCols;
+            const int gy = y0 + r, gx = x0 + c;
+            rin[q] = e < FuRegion<0>::kPix && gy >= 0 && gy < H && gx >= 0 && gx < W;
+            const size_t p = rin[q] ? (size_t)gy * W + gx : 0;
+            rx_[q][0] = rin[q] ? raw.eta[p] : 0.f;
+            rx_[q][1] = rin[q] ? raw.u[p] : 0.f;
+            rx_[q][2] = rin[q] ? raw.v[p] : 0.f;
+            rx_[q][3] = rin[q] ? raw.H[p] : 0.f;
+            rx_[q][4] = rin[q] ? (raw.mask[p] ? 1.f : 0.f) : 0.f;
+        }
+    };
+    auto commit = [&]() {
+#pragma unroll
+        for (int q = 0; q < kFuRawPer; ++q) {
+            const int e = threadIdx.x + q * kFuThreads;
+            if (e < FuRegion<0>::kPix) {
+                uint4 ca = make_uint4(0u, 0u, 0u, 0u), cb = make_uint4(0u, 0u, 0u, 0u);
+                if (rin[q]) pack_values(rx_[q], 0, nrm, ca, cb);  // no noise at inference
+                uint4* dst = reinterpret_cast<uint4*>(bufB + e * FuRegion<0>::kStride);
+                dst[0] = ca;
+                dst[1] = cb;
+            }
+        }
+    };
+    // The next layer's weights go from global memory straight into the free LDS slot while
+    // the current layer runs (a wave copies 64 consecutive 16 B chunks per load; the chunk
+    // counts are multiples of 64); the wait and the barrier after the layer publish them, and
+    // each wave then reads its A operands from LDS.
+    auto wstage = [&](int layer, unsigned char* slot) {
+        const int chunks = 9 * 32 * (layer == 0 ? 16 : 32) / 8;
+        const uint4* src = reinterpret_cast<const uint4*>(net.wk[layer]);
+#pragma unroll
+        for (int q = 0; q < kFuWPer; ++q) {
+            const int first = q * kFuThreads + wave * 64;  // wave-uniform
+            if (first < chunks)
+                __builtin_amdgcn_global_load_lds(src + first + lane, reinterpret_cast<uint4*>(slot) + first, 16, 0, 0);
+        }
+    };
+    auto publish = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies (and loads) have landed
+        __syncthreads();
+    };
+
+    bf16x8 w[9][2];
+    wstage(0, wslot[0]);
+    if ((int)blockIdx.x < total) {
+        fetch(blockIdx.x);
+        commit();
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+        const int y0 = ty * kFuTH, x0 = tx * kFuTW;
+        const int next = tile + (int)gridDim.x;
+        __syncthreads();  // packed input and layer 1's weights in place; the last tile's layer 4 done
+        fused_weights<16>(w, wslot[0], half, j);
+        wstage(1, wslot[1]);
+        fused_layer<1, 16, false>(bufB, bufA, w, bias_lds, nullptr, y0, x0, H, W, wave, half, j);
+        publish();
+        fused_weights<32>(w, wslot[1], half, j);
+        wstage(2, wslot[0]);
+        if (next < total) fetch(next);
+        fused_layer<2, 32, false>(bufA, bufB, w, bias_lds + 32, nullptr, y0, x0, H, W, wave, half, j);
+        publish();
+        fused_weights<32>(w, wslot[0], half, j);
+        wstage(3, wslot[1]);
+        fused_layer<3, 32, false>(bufB, bufA, w, bias_lds + 64, nullptr, y0, x0, H, W, wave, half, j);
+        publish();
+        fused_weights<32>(w, wslot[1], half, j);
+        wstage(0, wslot[0]);
+        if (next < total) commit();  // buffer B is free: layer 4 reads buffer A only
+        fused_layer<4, 32, true>(bufA, nullptr, w, bias_lds + 96, out_f, y0, x0, H, W, wave, half, j);
+        __builtin_amdgcn_s_waitcnt(0);
     }
 }
 
@@ -707,6 +927,16 @@ hipError_t launch_conv3x3_correct(const uint16_t* in, const uint16_t* Wk, const 
     if (cap < 1) return hipErrorInvalidDeviceFunction;
     hipLaunchKernelGGL((conv3x3_kernel<32, kConvCorrect>), dim3(tiles < cap ? tiles : cap), dim3(kConvThreads), 0, s,
                        in, Wk, bias, nullptr, nullptr, nullptr, H, W, 1, RawIn{}, InputNorm{}, co);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_fused(const RawIn& raw, const InputNorm& nrm, const FusedNet& net, float* out_f, int H,
+                            int W, hipStream_t s) {
+    const int tiles = ((W + kFuTW - 1) / kFuTW) * ((H + kFuTH - 1) / kFuTH);
+    const int cap = resident_groups(reinterpret_cast<const void*>(&cnn_fused_kernel), kFuThreads);
+    if (cap < 1) return hipErrorInvalidDeviceFunction;
+    hipLaunchKernelGGL(cnn_fused_kernel, dim3(tiles < cap ? tiles : cap), dim3(kFuThreads), 0, s, raw, nrm, net, out_f,
+                       H, W);
     return hipGetLastError();
 }
 

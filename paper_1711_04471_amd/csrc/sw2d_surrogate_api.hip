@@ -93,6 +93,50 @@ int sw2d_conv3x3_fwd_raw(const float* eta, const float* u, const float* v, const
                 "sw2d_conv3x3_fwd_raw");
 }
 
+int sw2d_cnn_forward(const float* eta, const float* u, const float* v, const float* H, const uint8_t* mask,
+                     int32_t nx, int32_t ny, const float* mean, const float* std_, const uint16_t* const* wk,
+                     const float* const* bias, float* out, void* stream) {
+    if (!eta || !u || !v || !H || !mask || !mean || !std_ || !wk || !bias || !out) return SW2D_EINVAL;
+    if (!dims_ok(1, ny, nx)) return SW2D_EINVAL;
+    FusedNet net;
+    for (int l = 0; l < 4; ++l) {
+        if (!wk[l] || !bias[l] || !aligned16(wk[l]) || !aligned16(bias[l])) return SW2D_EINVAL;
+        net.wk[l] = wk[l];
+        net.bias[l] = bias[l];
+    }
+    InputNorm nrm;
+    nrm.noise_amp = 0.f;
+    nrm.noise_seed = 0;
+    for (int c = 0; c < 5; ++c) {
+        if (!(std_[c] > 0.f) || !std::isfinite(mean[c])) return SW2D_EINVAL;
+        nrm.mean[c] = mean[c];
+        nrm.inv_std[c] = 1.f / std_[c];
+    }
+    return fail(launch_cnn_fused(RawIn{eta, u, v, H, mask}, nrm, net, out, ny, nx, static_cast<hipStream_t>(stream)),
+                "sw2d_cnn_forward");
+}
+
+int sw2d_surrogate_advance(sw2d_t coarse, int32_t nsteps, const float* H, const uint8_t* mask, const float* mean,
+                           const float* std_, const uint16_t* const* wk, const float* const* bias, const float* t_std,
+                           float* delta) {
+    hipStream_t s = nullptr;
+    int nx = 0, ny = 0;
+    if (!sw2d::detail::handle_info(coarse, &s, &nx, &ny) || nsteps < 0) return SW2D_ESTATE;
+    if (!H || !mask || !mean || !std_ || !wk || !bias || !t_std || !delta) return SW2D_EINVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(t_std[c])) return SW2D_EINVAL;
+    for (int32_t n = 0; n < nsteps; ++n) {
+        float *e, *u, *v;
+        int rc = sw2d_state(coarse, &e, &u, &v);
+        if (rc == SW2D_OK) rc = sw2d_cnn_forward(e, u, v, H, mask, nx, ny, mean, std_, wk, bias, delta, s);
+        if (rc == SW2D_OK) rc = sw2d_step(coarse, 1);
+        if (rc == SW2D_OK) rc = sw2d_state(coarse, &e, &u, &v);
+        if (rc == SW2D_OK) rc = fail(launch_correct(e, u, v, delta, mask, ny, nx, t_std, s), "sw2d_surrogate_advance");
+        if (rc != SW2D_OK) return rc;
+    }
+    return SW2D_OK;
+}
+
 int sw2d_conv3x3_correct(const uint16_t* in, const uint16_t* wk, const float* bias, const float* t_std,
                          const uint8_t* mask, float* eta, float* u, float* v, int32_t nx, int32_t ny, void* stream) {
     if (!in || !wk || !bias || !t_std || !mask || !eta || !u || !v || !aligned16(in) || !aligned16(wk))

@@ -136,6 +136,25 @@ class ConvNet:
                   "sw2d_conv3x3_fwd")
         return acts[2]
 
+    def forward_fused(self, eta, u, v, H, mask, h, w, mean_ptr, std_ptr):
+        """All four layers of one image from the raw coarse state in one kernel (the maps stay
+        on chip). Returns the FP32 output planes [1][3][h][w]."""
+        _, _, out, _ = self._buffers(1, h, w)
+        wk = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in self.wk])
+        bias = (ctypes.c_void_p * 4)(*[self.weight(layer)[1].data_ptr() for layer in range(4)])
+        check(self.lib.sw2d_cnn_forward(_p(eta), _p(u), _p(v), _p(H), _p(mask), w, h, mean_ptr, std_ptr, wk, bias,
+                                        _p(out), self.stream()), "sw2d_cnn_forward")
+        return out
+
+    def advance(self, sim, nsteps, H, mask, mean_ptr, std_ptr, tstd_ptr):
+        """nsteps corrected coarse steps on the coarse handle ``sim`` in one library call: the
+        fused network on the state before each step, the step, then the correction."""
+        _, _, out, _ = self._buffers(1, sim.ny, sim.nx)
+        wk = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in self.wk])
+        bias = (ctypes.c_void_p * 4)(*[self.weight(layer)[1].data_ptr() for layer in range(4)])
+        check(self.lib.sw2d_surrogate_advance(sim._handle(), int(nsteps), _p(H), _p(mask), mean_ptr, std_ptr, wk, bias,
+                                              tstd_ptr, _p(out)), "sw2d_surrogate_advance")
+
     def correct(self, hidden, eta, u, v, mask, h, w, tstd_ptr):
         """Layer 4 with its output added to the state as the correction (fused)."""
         check(self.lib.sw2d_conv3x3_correct(_p(hidden), _p(self.wk[3]), _p(self.weight(3)[1]), tstd_ptr, _p(mask),
@@ -435,17 +454,12 @@ def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1
     for seg in range(n_coarse // judge_every):
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        for _ in range(judge_every):
-            if net is None:
-                co.sim.step(1)
-                continue
-            # the network sees the state before the coarse step, as in training; layer 1
-            # packs the raw state itself and layer 4 adds its output to the stepped state
-            e, u, v = co.sim.state()
-            hidden = net.forward_hidden_raw(e, u, v, co.H, co.mask, co.ny, co.nx, mp, sp)
-            co.sim.step(1)
-            e, u, v = co.sim.state()
-            net.correct(hidden, e, u, v, co.mask, co.ny, co.nx, tp)
+        if net is None:
+            co.sim.step(judge_every)
+        else:
+            # the network sees the state before each coarse step, as in training; one kernel
+            # runs all four layers and its output corrects the stepped state
+            net.advance(co.sim, judge_every, co.H, co.mask, mp, sp, tp)
         torch.cuda.synchronize(dev)
         t1 = time.perf_counter()
         fine.step(4 * judge_every)

@@ -334,3 +334,48 @@ def test_fused_first_and_last_layers_equal_the_unfused_path(rng, shape):
     torch.cuda.synchronize()
     for x, y in zip(state, s2):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("shape", [(1024, 1024), (37, 45), (16, 32), (17, 33), (3, 5), (130, 257)])
+def test_fused_network_equals_the_layer_by_layer_chain(rng, shape):
+    """The one-kernel forward (maps kept in LDS, tiles grown by the receptive field ahead of
+    each layer) equals pack_input and the four layer kernels bit for bit, tile edges, image
+    edges and ragged tails included; the layer kernels are pinned to the oracle above."""
+    H, W = shape
+    print(f"fused forward {H}x{W}", flush=True)
+    fields = [rng.standard_normal((H, W)).astype(np.float32) for _ in range(4)]
+    mask = (rng.uniform(size=(H, W)) < 0.8).astype(np.uint8)
+    mean = np.array([0.1, -0.2, 0.3, 20.0, 0.5], dtype=np.float32)
+    std = np.array([0.5, 0.25, 2.0, 10.0, 0.5], dtype=np.float32)
+    mp = mean.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    sp = std.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    g = [torch.as_tensor(a).to(DEV) for a in fields] + [torch.as_tensor(mask).to(DEV)]
+    wks, biases = [], []
+    for cin, real_in, real_out, scale in ((16, 5, 32, 0.3), (32, 32, 32, 0.1), (32, 32, 32, 0.1), (32, 32, 3, 0.05)):
+        Wm = torch.from_numpy(wk_layout(rng.standard_normal((real_out, real_in, 3, 3)) * scale, cin)
+                              .astype(np.float32)).to(DEV)
+        wk = torch.empty((9, 32, cin), dtype=torch.bfloat16, device=DEV)
+        check(lib().sw2d_cast_weights(ptr(Wm), cin, ptr(wk), None, stream()))
+        b = torch.zeros(32, dtype=torch.float32, device=DEV)
+        b[:real_out] = torch.from_numpy((rng.standard_normal(real_out) * 0.1).astype(np.float32))
+        wks.append(wk)
+        biases.append(b)
+    # layer by layer
+    x = torch.empty((H, W, 16), dtype=torch.bfloat16, device=DEV)
+    check(lib().sw2d_pack_input(*map(ptr, g), W, H, mp, sp, ctypes.c_float(0.0), ctypes.c_uint64(0), ptr(x),
+                                stream()))
+    for layer in range(3):
+        y = torch.empty((H, W, 32), dtype=torch.bfloat16, device=DEV)
+        check(lib().sw2d_conv3x3_fwd(ptr(x), 16 if layer == 0 else 32, ptr(wks[layer]), ptr(biases[layer]), 1,
+                                     ptr(y), 1, H, W, stream()))
+        x = y
+    ref = torch.empty((1, 3, H, W), dtype=torch.float32, device=DEV)
+    check(lib().sw2d_conv3x3_fwd(ptr(x), 32, ptr(wks[3]), ptr(biases[3]), 0, ptr(ref), 1, H, W, stream()))
+    # one kernel
+    out = torch.full((1, 3, H, W), float("nan"), dtype=torch.float32, device=DEV)
+    wk_arr = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in wks])
+    b_arr = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in biases])
+    check(lib().sw2d_cnn_forward(*map(ptr, g), W, H, mp, sp, wk_arr, b_arr, ptr(out), stream()))
+    torch.cuda.synchronize()
+    assert torch.isfinite(ref).all()
+    assert torch.equal(ref.view(torch.int32), out.view(torch.int32))

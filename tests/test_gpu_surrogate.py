@@ -162,3 +162,30 @@ def test_trained_network_gains_over_coarse_only(trained):
         ratios.append(cnn / base)
     print(json.dumps({"rmse_ratio_cnn_over_coarse": ratios}), flush=True)
     assert np.mean(ratios) < 0.92 and max(ratios) < 1.05, ratios
+
+
+def test_advance_equals_the_layer_by_layer_steps(trained):
+    """The one-call corrected steps (one kernel for the network, the coarse step, the
+    correction) give bitwise the state of the layer-by-layer path step by step."""
+    net, _ = trained
+    case = S.fine_basin(50301, FINE)
+    fine = S.Sw2d.from_case(case)
+    st = net.stats
+    mean_a, mp = S._fptr(st.in_mean)
+    std_a, sp = S._fptr(st.in_std)
+    tstd_a, tp = S._fptr(st.t_std * 0.5)
+    a, b = S.Coarse(fine, case), S.Coarse(fine, case)
+    for _ in range(7):
+        e, u, v = a.sim.state()
+        hidden = net.forward_hidden_raw(e, u, v, a.H, a.mask, a.ny, a.nx, mp, sp)
+        a.sim.step(1)
+        e, u, v = a.sim.state()
+        net.correct(hidden, e, u, v, a.mask, a.ny, a.nx, tp)
+    net.advance(b.sim, 7, b.H, b.mask, mp, sp, tp)
+    torch.cuda.synchronize()
+    for x, y in zip(a.sim.state(), b.sim.state()):
+        assert torch.equal(x, y)
+    assert a.sim.steps_done == b.sim.steps_done == 7
+    a.sim.close()
+    b.sim.close()
+    fine.close()
