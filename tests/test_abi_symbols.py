@@ -98,3 +98,27 @@ def test_sor_argument_checks_need_no_gpu():
     # a short workspace is refused before any launch
     assert lib.sw2d_sor_run(ctypes.byref(good), ctypes.c_void_p(16), ctypes.c_void_p(16), 50, None,
                             ctypes.c_void_p(16), nb - 1, None) == -5
+
+
+def test_surrogate_entry_points_check_arguments_on_the_host(lib):
+    """The one-kernel network and the corrected-step loop refuse missing pointers, bad
+    normalisation and a missing handle before any device call."""
+    import ctypes
+
+    from paper_1711_04471_amd import _lib
+    L = _lib.load()
+    fp = ctypes.POINTER(ctypes.c_float)
+    mean = (ctypes.c_float * 5)(0, 0, 0, 0, 0)
+    std = (ctypes.c_float * 5)(1, 1, 1, 1, 1)
+    bad_std = (ctypes.c_float * 5)(1, 1, 0, 1, 1)
+    dummy = ctypes.c_void_p(256)
+    wk = (ctypes.c_void_p * 4)(256, 256, 256, 256)
+    bias = (ctypes.c_void_p * 4)(256, 256, 256, 256)
+    no_w = (ctypes.c_void_p * 4)(256, None, 256, 256)
+    args = [dummy] * 5
+    assert L.sw2d_cnn_forward(*args, 8, 8, mean, std, wk, bias, None, None) == _lib.SW2D_EINVAL
+    assert L.sw2d_cnn_forward(*args, 8, 8, mean, bad_std, wk, bias, dummy, None) == _lib.SW2D_EINVAL
+    assert L.sw2d_cnn_forward(*args, 8, 8, mean, std, no_w, bias, dummy, None) == _lib.SW2D_EINVAL
+    assert L.sw2d_cnn_forward(*args, 0, 8, mean, std, wk, bias, dummy, None) == _lib.SW2D_EINVAL
+    t_std = (ctypes.c_float * 3)(1, 1, 1)
+    assert L.sw2d_surrogate_advance(None, 1, dummy, dummy, mean, std, wk, bias, t_std, dummy) == _lib.SW2D_ESTATE
