@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 
+#include "sw2d_handle.h"
 #include "sw2d_internal.h"
 
 using namespace sw2d;

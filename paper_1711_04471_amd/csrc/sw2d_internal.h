@@ -119,8 +119,6 @@ namespace detail {
 bool params_valid(const sw2d_params* p);
 StepCoef make_coef(const sw2d_params* p);
 void set_hip_message(const char* msg);
-// The stream and grid size of a single-grid handle (false for a null handle).
-bool handle_info(sw2d_t h, hipStream_t* stream, int* nx, int* ny);
 }  // namespace detail
 
 }  // namespace sw2d

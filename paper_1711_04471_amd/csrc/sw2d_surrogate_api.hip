@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "sw2d_internal.h"
+#include "sw2d_handle.h"
 #include "sw2d_surrogate.h"
 
 using namespace sw2d;
