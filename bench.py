@@ -65,8 +65,10 @@ def parse():
     return ap.parse_args()
 
 
-def copy_probe():
-    """A plain device copy of known size: 1 GiB read + 1 GiB written per launch."""
+def copy_probe(quiet=False):
+    """A plain device copy of known size: 1 GiB read + 1 GiB written per launch (torch's copy
+    kernel): the practical HBM ceiling beside the step kernels, and the calibration of the
+    traffic counters."""
     import torch
     n = 1 << 28
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -82,8 +84,13 @@ def copy_probe():
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"probe": "device copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
-                      "ms": round(ms, 4), "GBs": round(8 * n / ms / 1e6, 1)}), flush=True)
+    rec = {"probe": "device copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+           "ms": round(ms, 4), "GBs": round(8 * n / ms / 1e6, 1)}
+    del a, b
+    torch.cuda.empty_cache()
+    if not quiet:
+        print(json.dumps(rec), flush=True)
+    return rec
 
 
 # band heights measured best per workload and steps per pass (sweep of 16..128 rows)
@@ -470,6 +477,7 @@ def main():
         out["sor"] = sor_leg(args, log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    out["roofline"]["device_copy_GBs"] = copy_probe(quiet=True)["GBs"]
     print(json.dumps(out), flush=True)
 
 
