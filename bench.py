@@ -140,8 +140,20 @@ def cpu_baseline(case, target_s):
     sw2d_ref.run_case(case, nsteps=n, nthreads=threads)
     dt = time.perf_counter() - t0
     return {"value": case.nx * case.ny * n / dt / 1e6, "unit": "Mcell-steps/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{case.name} full grid, {n} steps with folds, FP64, {dt:.1f} s"}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the baseline's context."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 BATCH_PASS = 3  # steps per pass of the batched kernel
