@@ -23,10 +23,14 @@
 // a captured graph of launches can be replayed without host-side parameters.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
+#include <queue>
+#include <utility>
 #include <vector>
 
 #include "sw2d_internal.h"
@@ -80,6 +84,8 @@ constexpr int kBatchRing = 64;  // steps of per-instance folds kept
 struct BatchArgs {
     const BatchInst* inst;
     const BatchTile* tiles;
+    const int* order;      // tile ids grouped by workgroup
+    const int2* wg_range;  // [grid]: first position in order, tile count
     FoldPartial* part;  // [2][K][n_tiles]
     sw2d_red* ring;     // [kBatchRing][n_inst]
     BatchControl* ctl;
@@ -211,6 +217,7 @@ __device__ __forceinline__ float uniform_f(float x) {
 template <int K>
 __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) {
     __shared__ BatchTile s_tiles[kLdsTiles];
+    __shared__ int s_ids[kLdsTiles];
     __shared__ double s_disp[kWavesPerGroup];
     __shared__ float s_mu[kWavesPerGroup], s_mv[kWavesPerGroup];
     constexpr int kOut = (K == 1) ? kStripOut : kWave - 4 * K;
@@ -221,15 +228,17 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
     const long long base = a.ctl->steps_done;
     const long long pbase = a.ctl->passes_done;
     const int passes = a.steps / K;
-    // this workgroup's tiles are lwg, lwg + nwg, ...
-    const int my_tiles = lwg < a.n_tiles ? (a.n_tiles - lwg + nwg - 1) / nwg : 0;
+    // this workgroup's tiles: order[first .. first + count), balanced by cost on the host
+    const int2 range = a.wg_range[lwg];
+    const int my_tiles = range.y;
     auto stage = [&](int k0) {  // descriptors k0 .. k0 + kLdsTiles - 1 of this workgroup
         const int n = min(kLdsTiles, my_tiles - k0);
         constexpr int kChunks = sizeof(BatchTile) / 16;
         for (int e = threadIdx.x; e < n * kChunks; e += kBatchThreads) {
             const int k = e / kChunks, ch = e - k * kChunks;
-            reinterpret_cast<uint4*>(&s_tiles[k])[ch] =
-                reinterpret_cast<const uint4*>(a.tiles + (size_t)lwg + (size_t)(k0 + k) * nwg)[ch];
+            const int id = a.order[range.x + k0 + k];
+            reinterpret_cast<uint4*>(&s_tiles[k])[ch] = reinterpret_cast<const uint4*>(a.tiles + id)[ch];
+            if (ch == 0) s_ids[k] = id;
         }
         __syncthreads();
     };
@@ -290,7 +299,7 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
                         marchK<K, true>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, F);
                 }
             }
-            const int it = lwg + k * nwg;
+            const int it = s_ids[kl];
 #pragma unroll
             for (int s = 0; s < K; ++s) {
                 double f_disp = F[s].disp;
@@ -343,6 +352,10 @@ struct sw2d_bctx {
     hipStream_t capture;        // private stream used only to record graphs
     BatchInst* d_inst;
     BatchTile* d_tiles;
+    int* d_order;         // tile ids grouped by workgroup
+    int2* d_wg_range;     // [kMaxBatchGrid]
+    std::vector<int> tile_cost;  // per tile: rows marched x strips, the balancing weight
+    int assigned_grid;    // grid the current assignment was made for (-1: none)
     FoldPartial* d_part;
     sw2d_red* d_ring;
     BatchControl* d_ctl;
@@ -385,7 +398,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct BatchLayout {
     std::vector<size_t> hp;  // per instance
-    size_t flags, scratch, inst, tiles, part, ring, ctl, gflags, total;
+    size_t flags, scratch, inst, tiles, order, range, part, ring, ctl, gflags, total;
     int n_tiles;
     std::vector<int> tiles_of;  // per instance
 };
@@ -434,6 +447,10 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
     off = align_up(off + (size_t)n * sizeof(BatchInst));
     L.tiles = off;
     off = align_up(off + (size_t)L.n_tiles * sizeof(BatchTile));
+    L.order = off;
+    off = align_up(off + (size_t)L.n_tiles * sizeof(int));
+    L.range = off;
+    off = align_up(off + (size_t)kMaxBatchGrid * sizeof(int2));
     L.part = off;
     off = align_up(off + 2 * (size_t)kMaxBatchK * L.n_tiles * sizeof(FoldPartial));
     L.ring = off;
@@ -450,6 +467,8 @@ int enqueue_chunks(sw2d_bctx* b, int32_t nsteps, hipStream_t s) {
     BatchArgs a;
     a.inst = b->d_inst;
     a.tiles = b->d_tiles;
+    a.order = b->d_order;
+    a.wg_range = b->d_wg_range;
     a.part = b->d_part;
     a.ring = b->d_ring;
     a.ctl = b->d_ctl;
@@ -484,6 +503,7 @@ int enqueue_chunks(sw2d_bctx* b, int32_t nsteps, hipStream_t s) {
 // written to the device with the members' tile ranges.
 int upload_tiles(sw2d_bctx* b, int K) {
     std::vector<BatchTile> tiles;
+    std::vector<int> cost;
     const int out = batch_strip_out(K);
     for (int i = 0; i < b->n; ++i) {
         BatchInst& in = b->inst[i];
@@ -509,15 +529,56 @@ int upload_tiles(sw2d_bctx* b, int K) {
                     t.inst = i;
                     t.k = in.k;
                     tiles.push_back(t);
+                    const int strips_here = in.strips - kWavesPerGroup * gr;
+                    cost.push_back((t.j1 - t.j0 + 4 * K) *
+                                   (strips_here < kWavesPerGroup ? strips_here : kWavesPerGroup));
                 }
         in.tile_end = (int)tiles.size();
     }
     if (tiles.size() > b->tile_capacity) return SW2D_ENOSPC;
     b->n_tiles = (int)tiles.size();
+    b->tile_cost.swap(cost);
+    b->assigned_grid = -1;
     SW2D_BHIP(hipMemcpyAsync(b->d_inst, b->inst.data(), b->n * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
     SW2D_BHIP(hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
                              b->stream));
     SW2D_BHIP(hipStreamSynchronize(b->stream));
+    return SW2D_OK;
+}
+
+// Balances the tiles over the grid's workgroups by their cost (rows marched x strips):
+// longest first, each to the least loaded workgroup (ties: the lowest index, so runs of
+// equal tiles go to neighbouring workgroups, which share an XCD). Every pass waits for its
+// slowest workgroup, so the largest load sets the pass time.
+int assign_tiles(sw2d_bctx* b) {
+    if (b->assigned_grid == b->grid) return SW2D_OK;
+    const int G = b->grid, n = b->n_tiles;
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return b->tile_cost[x] > b->tile_cost[y]; });
+    typedef std::pair<long long, int> Load;  // (load, workgroup)
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int w = 0; w < G; ++w) heap.push(Load(0, w));
+    std::vector<std::vector<int>> of(G);
+    for (int i : idx) {
+        Load l = heap.top();
+        heap.pop();
+        of[l.second].push_back(i);
+        heap.push(Load(l.first + b->tile_cost[i], l.second));
+    }
+    std::vector<int> order;
+    order.reserve(n);
+    std::vector<int2> range((size_t)G);
+    for (int w = 0; w < G; ++w) {
+        std::sort(of[w].begin(), of[w].end());  // a workgroup walks its tiles in list order
+        range[w] = make_int2((int)order.size(), (int)of[w].size());
+        order.insert(order.end(), of[w].begin(), of[w].end());
+    }
+    SW2D_BHIP(hipStreamSynchronize(b->stream));  // launches in flight read the old assignment
+    if (n > 0) SW2D_BHIP(hipMemcpyAsync(b->d_order, order.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    SW2D_BHIP(hipMemcpyAsync(b->d_wg_range, range.data(), (size_t)G * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    SW2D_BHIP(hipStreamSynchronize(b->stream));
+    b->assigned_grid = G;
     return SW2D_OK;
 }
 
@@ -585,6 +646,9 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     char* w = static_cast<char*>(d_work);
     b->d_inst = reinterpret_cast<BatchInst*>(w + L.inst);
     b->d_tiles = reinterpret_cast<BatchTile*>(w + L.tiles);
+    b->d_order = reinterpret_cast<int*>(w + L.order);
+    b->d_wg_range = reinterpret_cast<int2*>(w + L.range);
+    b->assigned_grid = -1;
     b->d_flags = reinterpret_cast<unsigned long long*>(w + L.gflags);
     b->d_part = reinterpret_cast<FoldPartial*>(w + L.part);
     b->d_ring = reinterpret_cast<sw2d_red*>(w + L.ring);
@@ -701,6 +765,8 @@ int sw2d_batch_step(sw2d_batch_t b, int32_t nsteps) {
     if (!b || nsteps < 0) return SW2D_ESTATE;
     if (nsteps == 0) return SW2D_OK;
     if (nsteps % b->steps_per_pass != 0) return SW2D_EINVAL;
+    const int rc0 = assign_tiles(b);  // outside any capture: it copies to the device
+    if (rc0) return rc0;
     if (!b->use_graph) {
         int rc = enqueue_chunks(b, nsteps, b->stream);
         if (rc) return rc;
