@@ -190,6 +190,10 @@ typedef struct {
     int32_t nx, ny, nz; /* cells incl. the boundary layer, each >= 3, product < 2^31 */
     double dx, dy, dz;  /* spacings > 0 */
     double omega;       /* relaxation factor, 0 < omega < 2 */
+    int32_t fused;      /* 0: a red sweep then a black sweep per iteration; 1: one pass per
+                           iteration (new red values of a tile and its one-cell ring in on-chip
+                           memory, ping-pong arrays); the same state bit for bit, residual sums
+                           to rounding order */
 } sw2d_sor_params;
 
 /* Residual r = f - L p of the state after `iter` iterations (iter 0 = the initial state):

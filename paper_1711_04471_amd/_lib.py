@@ -35,7 +35,7 @@ assert ctypes.sizeof(sw2d_red) == 32
 class sw2d_sor_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
-                ("omega", ctypes.c_double)]
+                ("omega", ctypes.c_double), ("fused", ctypes.c_int32)]
 
 
 class sw2d_sor_res(ctypes.Structure):

@@ -22,6 +22,7 @@
 // r^2, max |r| as magnitude bits) are added per iteration in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -195,6 +196,167 @@ __global__ __launch_bounds__(kSorFoldThreads) void sor_fold_kernel(const SorPart
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// One whole iteration per launch (fused = 1): a workgroup owns a tile of kFuM colour positions
+// x kFuJ rows and a chunk of kFuZ planes, reads the old red and black arrays and writes the
+// new ones into the other pair (ping-pong, so no workgroup reads a value another one has
+// already replaced). Walking up its planes, it computes the new red values of the next plane
+// over the tile grown by one position and one row (the red neighbours of its black cells),
+// keeps three planes of them in LDS, and updates the black cells of the plane below from
+// them. Every red and black value is the expression of the two-sweep iteration, so the
+// state is bitwise that of sor_sweep_kernel<0> then <1>; the red residual of the previous
+// state and the black residual of the new one are folded as there (owned cells only).
+constexpr int kFuM = 32, kFuJ = 16, kFuZ = 16;
+constexpr int kFuThreads = kFuM * kFuJ;                    // one black cell per thread
+constexpr int kFuHm = kFuM + 2, kFuHj = kFuJ + 2;          // red halo region of a plane
+constexpr int kFuHalo = kFuHm * kFuHj;
+constexpr int kFuRedPer = (kFuHalo + kFuThreads - 1) / kFuThreads;
+
+struct SorFuGeometry {
+    int tm, tj, tz, nblocks;  // tiles along positions, rows, plane chunks
+};
+
+SorFuGeometry sor_fu_geometry(const SorGeometry& g) {
+    SorFuGeometry f;
+    f.tm = (g.w + kFuM - 1) / kFuM;
+    f.tj = (g.ny - 2 + kFuJ - 1) / kFuJ;
+    f.tz = (g.nz - 2 + kFuZ - 1) / kFuZ;
+    f.nblocks = f.tm * f.tj * f.tz;
+    return f;
+}
+
+__global__ __launch_bounds__(kFuThreads) void sor_iter_kernel(const float* __restrict__ R, const float* __restrict__ B,
+                                                              const float* __restrict__ FR, const float* __restrict__ FB,
+                                                              float* __restrict__ Rn, float* __restrict__ Bn,
+                                                              SorGeometry g, SorFuGeometry fg, SorCoef c,
+                                                              SorPartial* __restrict__ red_part,
+                                                              SorPartial* __restrict__ black_part) {
+#pragma clang fp contract(off)
+    __shared__ float s_red[3][kFuHalo];
+    __shared__ double s_sum[kFuThreads];
+    __shared__ unsigned s_max[kFuThreads];
+    const int nx = g.nx, ny = g.ny, nz = g.nz, w = g.w;
+    const size_t plane = (size_t)ny * w;
+    const int b = blockIdx.x;
+    const int tm = b % fg.tm, tj = (b / fg.tm) % fg.tj, tz = b / (fg.tm * fg.tj);
+    const int m0 = tm * kFuM, j0 = 1 + tj * kFuJ, k0 = 1 + tz * kFuZ;
+    const int k1 = min(k0 + kFuZ, nz - 1);  // planes [k0, k1) are this chunk's
+    const int t = threadIdx.x;
+    double acc_r = 0.0, acc_b = 0.0;
+    unsigned mx_r = 0u, mx_b = 0u;
+
+    // New red value of cell (m, j, k) (position m of the red array), from the old arrays;
+    // cells on the boundary layer keep their value. *res: its residual in the old state.
+    auto red_new = [&](int m, int j, int k, float* res) -> float {
+        const size_t o = ((size_t)k * ny + j) * w + m;
+        const float pc = R[o];
+        const int s = (j + k) & 1;
+        const int i = s + 2 * m;
+        if (i < 1 || i > nx - 2 || j < 1 || j > ny - 2 || k < 1 || k > nz - 2) return pc;
+        const float xm = B[o];
+        const float xo = s ? B[o + 1] : B[o - 1];
+        const float pE = s ? xo : xm, pW = s ? xm : xo;
+        const float fc = FR[o];
+        const float sx = pE + pW;
+        const float sy = B[o + w] + B[o - w];
+        const float sz = B[o + plane] + B[o - plane];
+        const float nb = fmaf(c.cz, sz, fmaf(c.cy, sy, c.cx * sx));
+        *res = fc - fmaf(-c.diag, pc, nb);
+        const float gs = (nb - fc) * c.inv_diag;
+        return fmaf(c.omega, gs - pc, pc);
+    };
+
+    // red halo items of this thread: item q -> (m, j) = (m0 - 1 + q % kFuHm, j0 - 1 + q / kFuHm)
+    auto red_plane = [&](int k) {
+        float* dst = s_red[(k + 3) % 3];
+#pragma unroll
+        for (int r = 0; r < kFuRedPer; ++r) {
+            const int q = t + r * kFuThreads;
+            if (q >= kFuHalo) break;
+            const int hm = q % kFuHm, hj = q / kFuHm;
+            const int m = m0 - 1 + hm, j = j0 - 1 + hj;
+            float v = 0.f;
+            if (m >= 0 && m < w && j >= 0 && j < ny && k >= 0 && k < nz) {
+                float res = 0.f;
+                v = red_new(m, j, k, &res);
+                const bool owned = hm >= 1 && hm <= kFuM && hj >= 1 && hj <= kFuJ && k >= k0 && k < k1;
+                const int i = ((j + k) & 1) + 2 * m;
+                if (owned && i >= 1 && i <= nx - 2 && j <= ny - 2) {
+                    Rn[((size_t)k * ny + j) * w + m] = v;
+                    acc_r += (double)res * (double)res;
+                    mx_r = max(mx_r, __float_as_uint(res) & 0x7fffffffu);
+                }
+            }
+            dst[q] = v;
+        }
+    };
+
+    // the black cell of this thread in plane k, from the new red values in LDS
+    const int bm = t % kFuM, bj = t / kFuM;
+    const int m = m0 + bm, j = j0 + bj;
+    auto black_plane = [&](int k) {
+        if (m >= w || j > ny - 2) return;
+        const size_t o = ((size_t)k * ny + j) * w + m;
+        const int s = (1 + j + k) & 1;
+        const int i = s + 2 * m;
+        if (i < 1 || i > nx - 2) return;
+        const float* rc = s_red[(k + 3) % 3];
+        const float* rd = s_red[(k + 2) % 3];
+        const float* ru = s_red[(k + 4) % 3];
+        const int h = (bj + 1) * kFuHm + (bm + 1);  // this position in the halo region
+        const float xm = rc[h];
+        const float xo = s ? rc[h + 1] : rc[h - 1];
+        const float pE = s ? xo : xm, pW = s ? xm : xo;
+        const float pc = B[o];
+        const float fc = FB[o];
+        const float sx = pE + pW;
+        const float sy = rc[h + kFuHm] + rc[h - kFuHm];
+        const float sz = ru[h] + rd[h];
+        const float nb = fmaf(c.cz, sz, fmaf(c.cy, sy, c.cx * sx));
+        const float gs = (nb - fc) * c.inv_diag;
+        const float pn = fmaf(c.omega, gs - pc, pc);
+        Bn[o] = pn;
+        const float r = fc - fmaf(-c.diag, pn, nb);
+        acc_b += (double)r * (double)r;
+        mx_b = max(mx_b, __float_as_uint(r) & 0x7fffffffu);
+    };
+
+    red_plane(k0 - 1);
+    red_plane(k0);
+    for (int k = k0; k < k1; ++k) {
+        __syncthreads();  // planes k - 1 and k are in LDS; the slot of k + 1 is free
+        red_plane(k + 1);
+        __syncthreads();
+        black_plane(k);
+    }
+
+    // fixed-order trees: red residual (previous state) and black residual (new state)
+    for (int pass = 0; pass < 2; ++pass) {
+        __syncthreads();
+        s_sum[t] = pass ? acc_b : acc_r;
+        s_max[t] = pass ? mx_b : mx_r;
+        __syncthreads();
+        for (int hh = kFuThreads / 2; hh > 0; hh >>= 1) {
+            if (t < hh) {
+                s_sum[t] += s_sum[t + hh];
+                s_max[t] = max(s_max[t], s_max[t + hh]);
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            SorPartial* q = (pass ? black_part : red_part) + b;
+            q->sum_r2 = s_sum[0];
+            q->max_bits = s_max[0];
+            q->pad = 0u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void sor_zero_kernel(SorPartial* __restrict__ p, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
+        p[e] = SorPartial{0.0, 0u, 0u};
+}
+
 thread_local char g_sor_msg[256] = "";
 
 int sor_fail(hipError_t e, const char* what) {
@@ -210,7 +372,7 @@ bool sor_params_ok(const sw2d_sor_params* p) {
     if ((int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31)) return false;
     for (double h : {p->dx, p->dy, p->dz})
         if (!(h > 0.0) || !std::isfinite(h)) return false;
-    return p->omega > 0.0 && p->omega < 2.0;
+    return p->omega > 0.0 && p->omega < 2.0 && (p->fused == 0 || p->fused == 1);
 }
 
 template <int COLOR, int MODE>
@@ -231,6 +393,13 @@ hipError_t launch_split(float* nat, float* red, float* black, const SorGeometry&
 
 size_t colour_floats(const SorGeometry& g) { return (size_t)g.nz * g.ny * g.w; }
 
+// partials per residual slot: the sweep grid's, or with fused = 1 the larger of both grids
+int part_stride(const sw2d_sor_params* p, const SorGeometry& g) {
+    if (!p->fused) return g.nblocks;
+    const int f = sor_fu_geometry(g).nblocks;
+    return f > g.nblocks ? f : g.nblocks;
+}
+
 }  // namespace
 }  // namespace sw2d
 
@@ -241,9 +410,10 @@ extern "C" {
 size_t sw2d_sor_workspace_bytes(const sw2d_sor_params* p, int32_t iters) {
     if (!sor_params_ok(p) || iters < 0) return 0;
     const SorGeometry g = sor_geometry(p->nx, p->ny, p->nz);
-    // red, black, f red, f black (16 B aligned each), then the residual partials
+    // red, black, f red, f black (and with fused = 1 a second red and black, 256 B aligned
+    // each), then the residual partials: iters + 1 slots per colour
     const size_t arr = (colour_floats(g) * sizeof(float) + 255) / 256 * 256;
-    return 4 * arr + 2 * (size_t)(iters + 1) * g.nblocks * sizeof(SorPartial);
+    return (p->fused ? 6 : 4) * arr + 2 * (size_t)(iters + 1) * part_stride(p, g) * sizeof(SorPartial);
 }
 
 int sw2d_sor_run(const sw2d_sor_params* p, float* d_p, const float* d_f, int32_t iters, sw2d_sor_res* d_res,
@@ -265,9 +435,41 @@ int sw2d_sor_run(const sw2d_sor_params* p, float* d_p, const float* d_f, int32_t
     float* B = reinterpret_cast<float*>(base + arr);
     float* FR = reinterpret_cast<float*>(base + 2 * arr);
     float* FB = reinterpret_cast<float*>(base + 3 * arr);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->fused) {
+        // one launch per iteration, ping-pong between (R, B) and (R2, B2)
+        float* R2 = reinterpret_cast<float*>(base + 4 * arr);
+        float* B2 = reinterpret_cast<float*>(base + 5 * arr);
+        const int stride = part_stride(p, g);
+        const SorFuGeometry fg = sor_fu_geometry(g);
+        auto* red = reinterpret_cast<SorPartial*>(base + 6 * arr);
+        SorPartial* black = red + (size_t)(iters + 1) * stride;
+        const size_t nparts = 2 * (size_t)(iters + 1) * stride;
+        hipLaunchKernelGGL(sor_zero_kernel, dim3((unsigned)std::min<size_t>((nparts + 255) / 256, 1024)), dim3(256), 0, s,
+                           red, nparts);
+        hipError_t e = hipGetLastError();
+        // both pairs start as the split state: the boundary layer is never written again
+        if (e == hipSuccess) e = launch_split(d_p, R, B, g, 0, s);
+        if (e == hipSuccess) e = launch_split(d_p, R2, B2, g, 0, s);
+        if (e == hipSuccess) e = launch_split(const_cast<float*>(d_f), FR, FB, g, 0, s);  // read only (dir 0)
+        if (e == hipSuccess) e = launch_sweep<1, kSorResidualOnly>(B, R, FB, g, c, black, s);  // black part of state 0
+        for (int32_t n = 0; n < iters && e == hipSuccess; ++n) {
+            hipLaunchKernelGGL(sor_iter_kernel, dim3(fg.nblocks), dim3(kFuThreads), 0, s, R, B, FR, FB, R2, B2, g, fg,
+                               c, red + (size_t)n * stride, black + (size_t)(n + 1) * stride);
+            e = hipGetLastError();
+            std::swap(R, R2);
+            std::swap(B, B2);
+        }
+        if (e == hipSuccess) e = launch_sweep<0, kSorResidualOnly>(R, B, FR, g, c, red + (size_t)iters * stride, s);
+        if (e == hipSuccess) e = launch_split(d_p, R, B, g, 1, s);
+        if (e == hipSuccess && d_res) {
+            hipLaunchKernelGGL(sor_fold_kernel, dim3(iters + 1), dim3(kSorFoldThreads), 0, s, red, black, stride, d_res);
+            e = hipGetLastError();
+        }
+        return sor_fail(e, "sw2d_sor_run");
+    }
     auto* red = reinterpret_cast<SorPartial*>(base + 4 * arr);
     SorPartial* black = red + (size_t)(iters + 1) * g.nblocks;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_split(d_p, R, B, g, 0, s);
     if (e == hipSuccess) e = launch_split(const_cast<float*>(d_f), FR, FB, g, 0, s);  // read only (dir 0)
     if (e == hipSuccess) e = launch_sweep<1, kSorResidualOnly>(B, R, FB, g, c, black, s);  // black part of state 0

@@ -300,12 +300,13 @@ class SorSolver:
     boundary layer holds fixed values). Owns the workspace and residual buffer for a given
     iteration count; ``run`` updates ``p`` in place on the current torch stream."""
 
-    def __init__(self, nx, ny, nz, dx, dy, dz, omega, iters, device="cuda"):
+    def __init__(self, nx, ny, nz, dx, dy, dz, omega, iters, device="cuda", fused=False):
         self.lib = _lib.load()
         self.dev = torch.device(device)
         if self.dev.type == "cuda" and self.dev.index is None:
             self.dev = torch.device("cuda", torch.cuda.current_device())
-        self.p = _lib.sw2d_sor_params(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(omega))
+        self.p = _lib.sw2d_sor_params(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(omega),
+                                      int(bool(fused)))
         self.iters = int(iters)
         nb = self.lib.sw2d_sor_workspace_bytes(ctypes.byref(self.p), self.iters)
         if nb == 0:
@@ -314,8 +315,9 @@ class SorSolver:
         self.res = torch.empty((self.iters + 1) * SOR_RES_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
 
     @classmethod
-    def from_case(cls, case, device="cuda"):
-        return cls(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.omega, case.iters, device=device)
+    def from_case(cls, case, device="cuda", fused=False):
+        return cls(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.omega, case.iters, device=device,
+                   fused=fused)
 
     def run(self, p: torch.Tensor, f: torch.Tensor, residuals=True) -> None:
         for t in (p, f):

@@ -91,6 +91,9 @@ def test_sor_argument_checks_need_no_gpu():
         p = _lib.sw2d_sor_params(*args)
         assert lib.sw2d_sor_workspace_bytes(ctypes.byref(p), 10) == 0
         assert lib.sw2d_sor_run(ctypes.byref(p), None, None, 10, None, None, 0, None) == -1
+    assert lib.sw2d_sor_workspace_bytes(ctypes.byref(_lib.sw2d_sor_params(5, 5, 5, 1.0, 1.0, 1.0, 1.5, 2)), 10) == 0
+    fused = _lib.sw2d_sor_params(300, 300, 90, 4.0, 4.0, 2.0, 1.7, 1)
+    assert lib.sw2d_sor_workspace_bytes(ctypes.byref(fused), 50) > 0
     good = _lib.sw2d_sor_params(300, 300, 90, 4.0, 4.0, 2.0, 1.7)
     nb = lib.sw2d_sor_workspace_bytes(ctypes.byref(good), 50)
     assert nb > 0
