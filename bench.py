@@ -4,12 +4,14 @@ One benchmark step = one model time step (predictor, flux-divergence surface upd
 Shapiro filter, velocity update and the per-step folds) of the 8192 x 8192 basin
 (dx = 250 m, seeded bathymetry, land disks and 8 bumps), with the state resident in HBM.
 value = nx * ny * steps / wall time, in Mcell-steps/s. By default the step kernel advances
-3 steps per pass over the grid (temporal blocking; the state equals single steps bit for
-bit and the folds are still taken every step). The roofline object prices one launch at
-its algorithmic bytes - read eta, u, v, H and write eta, u, v once, 28 B per cell - against
-MI355X's 8 TB/s, using the mean launch duration from HIP events recorded on the library's
-stream. cpu_baseline times the FP64 oracle on the host cores over a bounded number of
-steps of the same basin.
+4 steps per pass over the grid with two adjacent columns per lane (temporal blocking; the
+state equals single steps bit for bit and the folds are still taken every step). The
+roofline object prices one launch by its dominant bound, using the mean launch duration
+from HIP events recorded on the library's stream: for several steps per pass the vector
+ALUs (algorithmic FP32 operations against the FP32 vector peak), for one step per pass HBM
+(read eta, u, v, H and write eta, u, v once, 28 B per cell, against MI355X's 8 TB/s); the
+other bound is reported beside it. cpu_baseline times the FP64 oracle on the host cores
+over a bounded number of steps of the same basin.
 """
 import argparse
 import json
@@ -43,7 +45,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--band-rows", type=int, default=0,
                     help="band height (default: 16 for single steps, the tuned height for passes)")
-    ap.add_argument("--steps-per-pass", type=int, default=3, choices=[1, 2, 3, 4],
+    ap.add_argument("--steps-per-pass", type=int, default=4, choices=[1, 2, 3, 4],
                     help="time steps per pass over the grid (temporal blocking)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--batched-steps", type=int, default=1000)
@@ -93,17 +95,20 @@ def copy_probe(quiet=False):
     return rec
 
 
-# band heights measured best per workload and steps per pass (sweep of 16..128 rows)
-TUNED_ROWS = {("basin_8192", 1): 16, ("basin_8192", 2): 16, ("basin_8192", 3): 32, ("basin_8192", 4): 128,
-              ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 32}
+# band heights measured best per workload and steps per pass (sweeps in steps of 4 rows; the
+# throughput is a sawtooth in the band height, from how the last workgroups of a launch fill
+# the GPU)
+TUNED_ROWS = {("basin_8192", 1): 16, ("basin_8192", 2): 16, ("basin_8192", 3): 64, ("basin_8192", 4): 104,
+              ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 16}
 
 
 # the plain fine model the surrogate is compared with (and judged by): steps per pass, rows
-SURROGATE_PASS = (3, 32)
+SURROGATE_PASS = (4, 56)
 
 
 def kernel_name(spp):
-    return "sw2d_step_kernel<0>" if spp == 1 else f"sw2d_stepk_kernel<{spp}>"
+    # both workloads have an even number of columns: the 8-byte row-access instance
+    return "sw2d_step_kernel<0>" if spp == 1 else f"sw2d_stepk_pair_kernel<{spp}, true>"
 
 
 def counter_record(spp):
@@ -111,7 +116,7 @@ def counter_record(spp):
     VALU activity), or None when there is none for this kernel or its sources have changed
     since it was taken."""
     import hashlib
-    tag = "sw2d_step_kernel" if spp == 1 else f"sw2d_stepk{spp}_kernel"
+    tag = "sw2d_step_kernel" if spp == 1 else f"sw2d_stepk{spp}_pair_kernel"
     path = os.path.join(ROOT, "profiles", f"{tag}_basin_8192_traffic.json")
     if not os.path.exists(path):
         return None

@@ -36,6 +36,7 @@
 #include <stdint.h>
 
 #include "sw2d_internal.h"
+#include "sw2d_pair.h"
 #include "sw2d_tile.h"
 
 namespace sw2d {
@@ -201,6 +202,57 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
     }
 }
 
+// The same with two adjacent columns per lane: strips of 128 - 4K owned columns; kWide when
+// nx is even (8-byte row accesses). The register budget is held to SW2D_PAIR_WAVES waves per
+// SIMD.
+#ifndef SW2D_PAIR_WAVES
+#define SW2D_PAIR_WAVES 3
+#endif
+template <int K, bool kWide>
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(SW2D_PAIR_WAVES))) void sw2d_stepk_pair_kernel(
+    const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
+    const float* __restrict__ hp, float* __restrict__ eta_o, float* __restrict__ u_o,
+    float* __restrict__ v_o, FoldPartial* __restrict__ part, int stride, StepGeometry geo, StepCoef k) {
+    const int tile = tile_of_block(blockIdx.x, geo.nblocks);
+#if SW2D_BAND_BLOCK > 1
+    const int per_block = geo.groups_x * SW2D_BAND_BLOCK;
+    const int blk = tile / per_block;
+    const int rem = tile - blk * per_block;
+    const int nb = min(SW2D_BAND_BLOCK, geo.bands - blk * SW2D_BAND_BLOCK);
+    const int group = rem / nb;
+    const int band = blk * SW2D_BAND_BLOCK + (rem - group * nb);
+#else
+    const int band = tile / geo.groups_x;
+    const int group = tile - band * geo.groups_x;
+#endif
+    constexpr int kOut = 2 * kWave - 4 * K;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int strip = group * kWavesPerGroup + wave;
+    const int c0 = strip * kOut - 2 * K + 2 * lane;
+    const bool col_in = c0 >= 0 && c0 < geo.nx;
+    const bool owned = col_in && lane >= K && lane < kWave - K;
+    const int j0 = band * geo.rows;
+    const int j1 = min(j0 + geo.rows, geo.ny);
+
+    LaneFolds F[K];
+    if (strip < geo.strips) {
+#if SW2D_ZIGZAG
+        if (band & 1)
+            marchK_pair<K, false, kWide>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c0, col_in, owned, j0, j1,
+                                         k, F);
+        else
+#endif
+            marchK_pair<K, true, kWide>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c0, col_in, owned, j0, j1,
+                                        k, F);
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        if (s > 0) __syncthreads();
+        workgroup_fold(F[s].disp, F[s].mu(), F[s].mv(), part + (size_t)s * stride + blockIdx.x);
+    }
+}
+
 // Final level of the folds: one workgroup per step adds that step's partials in a
 // fixed order and writes the ring entry. h_sum = sum over water cells of H.
 __global__ __launch_bounds__(kFoldThreads) void sw2d_fold_kernel(const FoldPartial* __restrict__ part,
@@ -338,6 +390,27 @@ hipError_t launch_stepk(int K, const float* eta, const float* u, const float* v,
                         float* eta_o, float* u_o, float* v_o, FoldPartial* part, int stride,
                         const StepGeometry& geo, const StepCoef& k, hipStream_t s) {
     const dim3 grid(geo.nblocks), block(kGroupThreads);
+#if SW2D_PAIR_COLUMNS
+    const bool wide = (geo.nx % 2) == 0;
+#define SW2D_PAIR_CASE(KK)                                                                                         \
+    case KK:                                                                                                       \
+        if (wide)                                                                                                  \
+            hipLaunchKernelGGL((sw2d_stepk_pair_kernel<KK, true>), grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, \
+                               part, stride, geo, k);                                                              \
+        else                                                                                                       \
+            hipLaunchKernelGGL((sw2d_stepk_pair_kernel<KK, false>), grid, block, 0, s, eta, u, v, hp, eta_o, u_o,   \
+                               v_o, part, stride, geo, k);                                                         \
+        break;
+    switch (K) {
+        SW2D_PAIR_CASE(2)
+        SW2D_PAIR_CASE(3)
+        SW2D_PAIR_CASE(4)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef SW2D_PAIR_CASE
+    return hipGetLastError();
+#endif
     switch (K) {
         case 2:
             hipLaunchKernelGGL(sw2d_stepk_kernel<2>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, stride,

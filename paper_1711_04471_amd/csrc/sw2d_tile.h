@@ -61,6 +61,53 @@ __device__ __forceinline__ void store(float* p, float x) {
 #endif
 }
 
+// Formulas of the plain step (Sect. 6.2), written once and used by every row pipeline
+// whatever its lane layout. Contraction is off and each fused multiply-add is explicit.
+
+// Predicted velocity of an x-face from the surface of its west (e) and east (eE) cell:
+// u* = u - g dt/dx (eta_E - eta), zero on an inactive face.
+__device__ __forceinline__ float x_pred(float e, float eE, float ur, bool au, const StepCoef& k) {
+#pragma clang fp contract(off)
+    return au ? fmaf(-k.cx, eE - e, ur) : 0.f;
+}
+
+// Predicted velocity of a y-face from the surface of its south (e_lo) and north (e_hi) cell.
+__device__ __forceinline__ float y_pred(float e_lo, float e_hi, float v_lo, bool av, const StepCoef& k) {
+#pragma clang fp contract(off)
+    return av ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
+}
+
+// Upwind flux through a face: the velocity times the total depth of the cell it comes from
+// (h_lo for a positive velocity, h_hi otherwise); zero velocity gives zero flux.
+__device__ __forceinline__ float upwind_flux(float vel, float h_lo, float h_hi) {
+#pragma clang fp contract(off)
+    return vel * (vel > 0.f ? h_lo : h_hi);
+}
+
+// x-part of the surface update: pe = eta - dt/dx (Fx - Fx_W).
+__device__ __forceinline__ float x_update(float e, float fx, float fxW, const StepCoef& k) {
+#pragma clang fp contract(off)
+    return fmaf(-k.rx, fx - fxW, e);
+}
+
+// Predicted surface of a water cell: pe - dt/dy (Fy_N - Fy_S); zero on land.
+__device__ __forceinline__ float y_update(bool w, float fyN, float fyS, float pe, const StepCoef& k) {
+#pragma clang fp contract(off)
+    return w ? fmaf(-k.ry, fyN - fyS, pe) : 0.f;
+}
+
+// First-order Shapiro filter of the predicted surface es_c of a water cell across its
+// water neighbours, added east, west, north, south in that order; zero on land.
+__device__ __forceinline__ float shapiro_nb(float es_c, bool w_c, float esE, bool wE, float esW, bool wW,
+                                            float es_n, bool w_n, float es_s, bool w_s, float e4) {
+#pragma clang fp contract(off)
+    float s = wE ? esE - es_c : 0.f;
+    if (wW) s += esW - es_c;
+    if (w_n) s += es_n - es_c;
+    if (w_s) s += es_s - es_c;
+    return w_c ? fmaf(e4, s, es_c) : 0.f;
+}
+
 // Row r of the march: water flags, total depth, x-face predictor and flux, and the
 // x-part of the surface update (pe = eta - dt/dx (Fx - Fx_W)).
 struct RowX {
@@ -107,13 +154,13 @@ __device__ __forceinline__ RowX row_x(float e, float hpr, float ur, const StepCo
         o.dW = hW > k.hmin;
         o.us = (au && face_open(o.d, o.dE, e, eE)) ? fmaf(-k.cx, eE - e, ur) : 0.f;
     } else {
-        o.us = au ? fmaf(-k.cx, eE - e, ur) : 0.f;
+        o.us = x_pred(e, eE, ur, au, k);
     }
     if constexpr ((kVar & kVarFriction) != 0) o.us = au ? friction(o.us, ur, o.h, hpE + eE, k) : 0.f;
     // an inactive face has us = 0, so its flux is 0 without a second select
-    const float fx = o.us * (o.us > 0.f ? o.h : hpE + eE);
+    const float fx = upwind_flux(o.us, o.h, hpE + eE);
     const float fxW = from_west(fx);
-    o.pe = fmaf(-k.rx, fx - fxW, e);
+    o.pe = x_update(e, fx, fxW, k);
     return o;
 }
 
@@ -127,10 +174,10 @@ __device__ __forceinline__ void face_y(float v_lo, float e_lo, float h_lo, bool 
     if constexpr ((kVar & kVarWetDry) != 0) {
         vs = (av && face_open(h_lo > k.hmin, h_hi > k.hmin, e_lo, e_hi)) ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
     } else {
-        vs = av ? fmaf(-k.cy, e_hi - e_lo, v_lo) : 0.f;
+        vs = y_pred(e_lo, e_hi, v_lo, av, k);
     }
     if constexpr ((kVar & kVarFriction) != 0) vs = av ? friction(vs, v_lo, h_lo, h_hi, k) : 0.f;
-    fy = vs * (vs > 0.f ? h_lo : h_hi);  // vs = 0 on an inactive face
+    fy = upwind_flux(vs, h_lo, h_hi);  // vs = 0 on an inactive face
 }
 
 // First-order Shapiro filter of the predicted surface es_c across water neighbours
@@ -138,13 +185,7 @@ __device__ __forceinline__ void face_y(float v_lo, float e_lo, float h_lo, bool 
 __device__ __forceinline__ float shapiro(float es_c, bool w_c, bool wE, bool wW, float es_n, bool w_n,
                                          float es_s, bool w_s, float e4) {
 #pragma clang fp contract(off)
-    const float esE = from_east(es_c);
-    const float esW = from_west(es_c);
-    float s = wE ? esE - es_c : 0.f;
-    if (wW) s += esW - es_c;
-    if (w_n) s += es_n - es_c;
-    if (w_s) s += es_s - es_c;
-    return w_c ? fmaf(e4, s, es_c) : 0.f;
+    return shapiro_nb(es_c, w_c, from_east(es_c), wE, from_west(es_c), wW, es_n, w_n, es_s, w_s, e4);
 }
 
 // Wetting and drying: the filter acts on wet cells (d_c) across wet neighbours; a dry
@@ -211,7 +252,7 @@ struct Stage : std::conditional_t<(kVar & kVarWetDry) != 0, StageWetFlags, Stage
             float vs, fy;
             bool av;
             face_y<kVar>(v1, e1, h1, w1, X.e, X.h, X.w, k, vs, fy, av);
-            const float es = w1 ? fmaf(-k.ry, fy - fy2, pe1) : 0.f;
+            const float es = y_update(w1, fy, fy2, pe1, k);
             if constexpr (kWetDry) eta_o = shapiro_wd(es2, this->d2, this->dE2, this->dW2, es, this->d1, es3, this->d3, k.e4);
             else eta_o = shapiro(es2, w2, wE2, wW2, es, w1, es3, w3, k.e4);
             if constexpr (kFilterUV) {
@@ -239,7 +280,7 @@ struct Stage : std::conditional_t<(kVar & kVarWetDry) != 0, StageWetFlags, Stage
             float vs, fy;
             bool av;
             face_y<kVar>(vr, X.e, X.h, X.w, e1, h1, w1, k, vs, fy, av);
-            const float es = w1 ? fmaf(-k.ry, fy1 - fy, pe1) : 0.f;
+            const float es = y_update(w1, fy1, fy, pe1, k);
             if constexpr (kWetDry) eta_o = shapiro_wd(es2, this->d2, this->dE2, this->dW2, es3, this->d3, es, this->d1, k.e4);
             else eta_o = shapiro(es2, w2, wE2, wW2, es3, w3, es, w1, k.e4);
             if constexpr (kFilterUV) {

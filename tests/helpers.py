@@ -9,12 +9,15 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
-def gpu_run(case, nsteps=None, band_rows=None, k=None):
-    """Run a case through the C ABI; returns (eta, u, v, folds of the last k steps)."""
+def gpu_run(case, nsteps=None, band_rows=None, k=None, steps_per_pass=1):
+    """Run a case through the C ABI; returns (eta, u, v, folds of the last k steps). With
+    steps_per_pass > 1, band_rows is the band height of the temporally blocked passes."""
     from paper_1711_04471_amd.sw2d import Sw2d, ring_capacity
     n = case.steps if nsteps is None else nsteps
     with Sw2d.from_case(case) as sim:
-        if band_rows is not None:
+        if steps_per_pass > 1:
+            sim.set_time_blocking(steps_per_pass, rows=band_rows or 32)
+        elif band_rows is not None:
             sim.band_rows = band_rows
         sim.step(n)
         kk = min(n, ring_capacity()) if k is None else k

@@ -84,12 +84,20 @@ def test_basin_2048_1000_steps():
     np.testing.assert_allclose(red["max_abs_v"], ored[-1000:, 3], rtol=TOL)
 
 
+# the launch configuration the benchmark times on the 8192^2 basin: steps per pass, band rows
+BENCH_PASS = (4, 104)
+
+
 def test_basin_8192_500_steps_sampled_windows():
-    """The full 8192^2 headline run, checked on windows the oracle computes exactly from
-    their dependency cone, plus volume conservation over the whole basin."""
+    """The full 8192^2 headline run in the benchmark's launch configuration, checked on
+    windows the oracle computes exactly from their dependency cone, plus volume conservation
+    over the whole basin; the state equals single steps bit for bit."""
     c = inputs.basin_8192()
-    _say(f"case {c.name} {c.nx}x{c.ny} steps {c.steps}")
-    e, u, v, red = gpu_run(c)
+    _say(f"case {c.name} {c.nx}x{c.ny} steps {c.steps}, {BENCH_PASS[0]} steps per pass, {BENCH_PASS[1]} rows")
+    e, u, v, red = gpu_run(c, steps_per_pass=BENCH_PASS[0], band_rows=BENCH_PASS[1])
+    e1, u1, v1, red1 = gpu_run(c)
+    assert np.array_equal(e, e1) and np.array_equal(u, u1) and np.array_equal(v, v1)
+    np.testing.assert_allclose(red["vol_disp"], red1["vol_disp"], rtol=1e-12, atol=1e-9 * c.dx * c.dy)
     v0 = sw2d_ref.reduce(c.nx, c.ny, c.dx, c.dy, c.H, c.mask, c.eta, c.u, c.v)
     assert abs(red["vol_disp"][-1] - v0[1]) <= 1e-5 * abs(v0[1])
     assert abs(red["vol_total"][-1] - v0[0]) <= 1e-5 * abs(v0[1])
@@ -171,10 +179,13 @@ def test_restart_is_bitwise():
 
 
 @pytest.mark.parametrize("spp", [2, 3, 4])
-@pytest.mark.parametrize("shape,nsteps", [((700, 530), 37), ((61, 47), 20), ((300, 1201), 9), ((1000, 70), 1)])
+@pytest.mark.parametrize("shape,nsteps", [((700, 530), 37), ((61, 47), 20), ((300, 1201), 9), ((1000, 70), 1),
+                                          ((113, 40), 13), ((234, 41), 11)])
 def test_k_steps_per_pass_equal_single_steps(shape, nsteps, spp):
     """Temporal blocking keeps the intermediate state in registers; every state bit equals
-    single steps, the folds agree up to summation order and with the oracle."""
+    single steps, the folds agree up to summation order and with the oracle. Odd widths take
+    the 4-byte column-pair accesses, and 113 and 234 columns leave a last strip of one or two
+    owned columns (strips of 128 - 4K)."""
     from paper_1711_04471_amd.sw2d import Sw2d
     nx, ny = shape
     c = inputs.small_basin(nx, ny, seed=nx + ny, steps=nsteps)
