@@ -234,7 +234,13 @@ __device__ __forceinline__ void marchK_pair(const float* __restrict__ eta, const
     };
     int i = 0;
     for (; i < 4 * K; ++i) row(i, std::false_type{});
-    for (; i < n_rows; ++i) row(i, std::true_type{});
+    // Two rows per iteration: the pipeline's register shifts then mostly become renamings
+    // instead of moves.
+    for (; i + 1 < n_rows; i += 2) {
+        row(i, std::true_type{});
+        row(i + 1, std::true_type{});
+    }
+    if (i < n_rows) row(i, std::true_type{});
 }
 #endif
 

@@ -279,7 +279,7 @@ def make_dataset(seeds, n=4096, pairs_per_run=100, every=20, lead=4, device="cud
     for r, seed in enumerate(seeds):
         case = fine_basin(seed, n)
         with Sw2d.from_case(case, device=dev) as fine:
-            fine.set_time_blocking(3, rows=32)  # bitwise the same states, fewer passes
+            fine.set_time_blocking(4, rows=56)  # bitwise the same states, one pass per coarse step
             co = Coarse(fine, case)
             Hs[r].copy_(co.H)
             masks[r].copy_(co.mask)
