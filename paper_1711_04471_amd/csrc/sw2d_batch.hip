@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "sw2d_internal.h"
+#include "sw2d_pair.h"
 #include "sw2d_tile.h"
 
 namespace sw2d {
@@ -79,6 +80,22 @@ struct BatchControl {
 
 constexpr int kBatchThreads = kGroupThreads;
 constexpr int kMaxBatchK = 3;  // steps per pass of the batched kernel: 1..3
+// Two columns per lane for K >= 2 (as the single-grid K-step kernel) measured slower on the
+// ensemble (327,100 against 338,600 Mcell-steps/s at K = 3, 64-row bands): the members are
+// small, odd widths need 4-byte accesses, and the persistent grid drops from 4 to 3 resident
+// workgroups per CU. Off by default.
+#ifndef SW2D_BATCH_PAIR
+#define SW2D_BATCH_PAIR 0
+#endif
+#if SW2D_BATCH_PAIR
+#define SW2D_BATCH_WAVES __attribute__((amdgpu_waves_per_eu(3)))
+#else
+#define SW2D_BATCH_WAVES
+#endif
+// Owned columns of a strip for K steps per pass.
+constexpr int batch_strip_out(int K) {
+    return K == 1 ? kStripOut : (SW2D_BATCH_PAIR ? 2 * kWave : kWave) - 4 * K;
+}
 constexpr int kBatchRing = 64;  // steps of per-instance folds kept
 
 struct BatchArgs {
@@ -213,15 +230,19 @@ __device__ __forceinline__ float uniform_f(float x) {
 }
 
 // K steps per pass over each member (temporal blocking as in the single-grid K-step
-// kernel: strips own 64 - 4K columns, bands read a 2K-row halo); the grid meets once per pass.
+// kernel: bands read a 2K-row halo, strips lose 2K columns on each side); the grid meets once
+// per pass. For K >= 2 a lane holds two adjacent columns (SW2D_BATCH_PAIR: strips of 128 - 4K
+// owned columns, 4-byte row accesses since members may have odd widths), otherwise one.
 template <int K>
-__global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBatchThreads) SW2D_BATCH_WAVES void sw2d_batch_kernel(BatchArgs a) {
     __shared__ BatchTile s_tiles[kLdsTiles];
     __shared__ int s_ids[kLdsTiles];
     __shared__ double s_disp[kWavesPerGroup];
     __shared__ float s_mu[kWavesPerGroup], s_mv[kWavesPerGroup];
-    constexpr int kOut = (K == 1) ? kStripOut : kWave - 4 * K;
-    constexpr int kEdge = (K == 1) ? kHalo : 2 * K;
+    constexpr bool kPair = SW2D_BATCH_PAIR && K >= 2;
+    constexpr int kOut = batch_strip_out(K);
+    constexpr int kEdge = (K == 1) ? kHalo : 2 * K;  // unowned columns on each side of a strip
+    constexpr int kEdgeLanes = kPair ? K : kEdge;
     const int nwg = gridDim.x;
     const int lwg = logical_block(blockIdx.x, nwg);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -260,9 +281,10 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
             const int nx = uniform(t.nx), ny = uniform(t.ny);
             const int group2 = uniform(t.group2);
             const int strip = (group2 >> 1) * kWavesPerGroup + wave;
-            const int c = strip * kOut - kEdge + lane;
+            // this lane's (first) column
+            const int c = strip * kOut - kEdge + (kPair ? 2 * lane : lane);
             const bool col_in = c >= 0 && c < nx;
-            const bool out_lane = col_in && lane >= kEdge && lane < kWave - kEdge;
+            const bool out_lane = col_in && lane >= kEdgeLanes && lane < kWave - kEdgeLanes;
             LaneFolds F[K];
             if (strip < uniform(t.strips)) {
                 StepCoef kc;
@@ -292,6 +314,13 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
                     F[0].disp = f_disp;
                     F[0].mu_bits = __float_as_uint(f_mu);
                     F[0].mv_bits = __float_as_uint(f_mv);
+                } else if constexpr (kPair) {
+                    if (group2 & 1)
+                        marchK_pair<K, false, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0,
+                                                     j1, kc, F);
+                    else
+                        marchK_pair<K, true, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0,
+                                                    j1, kc, F);
                 } else {
                     if (group2 & 1)
                         marchK<K, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, F);
@@ -411,7 +440,6 @@ constexpr int kMaxBatchGrid = 256 * 8;  // flag lines reserved: 8 workgroups on 
 // its deadline. 6 keeps a margin below that bound.
 constexpr int kBatchWgPerCu = 6;
 
-int batch_strip_out(int K) { return K == 1 ? kStripOut : kWave - 4 * K; }
 
 int rows_for(const sw2d_params& p, const int32_t* band_rows, int i) {
     int r = band_rows ? band_rows[i] : 16;
@@ -431,8 +459,10 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
         if (rows < 1 || (band_rows && band_rows[i] < kMinRows)) return false;
         L.hp[i] = off;
         off = align_up(off + (size_t)p[i].nx * p[i].ny * sizeof(float));
-        // the narrowest strips (most tiles) are those of the largest K
-        const int strips = (p[i].nx + batch_strip_out(kMaxBatchK) - 1) / batch_strip_out(kMaxBatchK);
+        // the narrowest strips of any K give the most tiles
+        int narrow = batch_strip_out(1);
+        for (int K = 2; K <= kMaxBatchK; ++K) narrow = std::min(narrow, batch_strip_out(K));
+        const int strips = (p[i].nx + narrow - 1) / narrow;
         const int groups = (strips + kWavesPerGroup - 1) / kWavesPerGroup;
         const int bands = (p[i].ny + rows - 1) / rows;
         L.tiles_of[i] = groups * bands;
