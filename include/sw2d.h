@@ -85,7 +85,8 @@ enum {
 #define SW2D_ADVECTION 4u
 #define SW2D_WETDRY 8u
 
-/* Grid and constants. nx, ny count every cell, land border included (>= 3 each).
+/* Grid and constants. nx, ny count every cell, land border included (>= 3 each), with
+ * nx * ny <= 2^31 and nx <= 2^28 (a row is addressed with 32-bit byte offsets).
  * dx, dy, dt > 0 and finite; g >= 0 and finite; eps in [0, 1] (Shapiro weight);
  * flags: 0, a combination of SW2D_FRICTION, SW2D_FILTER_UV, SW2D_ADVECTION, or SW2D_WETDRY
  * alone; cd >= 0 and finite, the bottom-drag coefficient (used with SW2D_FRICTION, ignored

@@ -61,6 +61,7 @@ bool params_ok(const sw2d_params* p) {
     if (!p) return false;
     if (p->nx < 3 || p->ny < 3) return false;
     if ((int64_t)p->nx * p->ny > ((int64_t)1 << 31)) return false;
+    if (p->nx > (1 << 28)) return false;  // row byte offsets stay below the kernels' no-lane offset
     if (!finite_pos(p->dx) || !finite_pos(p->dy) || !finite_pos(p->dt)) return false;
     if (!std::isfinite(p->g) || p->g < 0.0) return false;
     if (!std::isfinite(p->eps) || p->eps < 0.0 || p->eps > 1.0) return false;

@@ -47,6 +47,11 @@ def test_host_only_calls(lib):
     assert L.sw2d_workspace_bytes(ctypes.byref(p)) > 66 * 66 * 4
     bad = _lib.sw2d_params(66, 66, 100.0, 100.0, 9.81, 5.0, 1.5, 0)
     assert L.sw2d_workspace_bytes(ctypes.byref(bad)) == 0
+    # rows wider than 2^28 cells are refused (32-bit row byte offsets), 2^28 itself is not
+    wide = _lib.sw2d_params((1 << 28) + 2, 3, 100.0, 100.0, 9.81, 5.0, 0.05, 0)
+    assert L.sw2d_workspace_bytes(ctypes.byref(wide)) == 0
+    edge = _lib.sw2d_params(1 << 28, 3, 100.0, 100.0, 9.81, 5.0, 0.05, 0)
+    assert L.sw2d_workspace_bytes(ctypes.byref(edge)) > 0
     assert L.sw2d_ring_capacity() >= 1000
     assert L.sw2d_strerror(-5).decode().startswith("workspace")
     assert L.sw2d_destroy(None) == 0
