@@ -316,7 +316,8 @@ def variants_leg(case, steps, log):
     """The single-step kernel with each model variant (bottom friction, velocity filter,
     advection, all three, wetting and drying) on the same basin: same 28 B per cell-step,
     more arithmetic per cell. The kernels take every decision with selects, not branches,
-    so their time does not depend on how many cells are dry."""
+    so their time does not depend on how many cells are dry. Friction and wetting/drying
+    are also timed at several steps per pass."""
     import torch
 
     from paper_1711_04471_amd.sw2d import ADVECTION, FILTER_UV, FRICTION, WETDRY, Sw2d
@@ -334,8 +335,24 @@ def variants_leg(case, steps, log):
         gbs = cells * BYTES_PER_CELL_STEP / (ms * 1e-3) / 1e9
         out[name] = {"ms_per_step": round(ms, 5), "value": round(cells / ms / 1e3, 1),
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    # the variants that also take several steps per pass (one column per lane), at their best
+    for name, flags in (("friction", FRICTION), ("wetdry", WETDRY)):
+        K, rows = VARIANT_PASS[name]
+        with Sw2d.from_case(case, flags=flags, cd=0.0025, hmin=0.0625) as sim:
+            sim.set_time_blocking(K, rows=rows)
+            sim.step(2 * K)
+            torch.cuda.synchronize()
+            ms = sim.step_timed(max(K, steps - steps % K))
+        out[f"{name}_{K}_per_pass"] = {"ms_per_step": round(ms, 5), "value": round(cells / ms / 1e3, 1),
+                                       "steps_per_pass": K, "band_rows": rows}
     log(f"variants: {out}")
-    return {"workload": f"{case.name}, one step per pass, cd=0.0025, hmin=0.0625", "unit": "Mcell-steps/s", **out}
+    return {"workload": f"{case.name}, one step per pass unless named, cd=0.0025, hmin=0.0625",
+            "unit": "Mcell-steps/s", **out}
+
+
+# steps per pass and band rows of the variants' K-step passes (best of K = 2..4 x rows 16..64
+# on the 8192^2 basin)
+VARIANT_PASS = {"friction": (2, 32), "wetdry": (3, 32)}
 
 
 SOR_BYTES_PER_CELL_ITER = 16  # read the other colour, own colour and own f; write own colour

@@ -82,7 +82,8 @@ Layout layout(const sw2d_params* p) {
     const size_t cells = (size_t)p->nx * p->ny;
     int cap = 0;
     for (int K = 1; K <= kMaxStepsPerPass; ++K) {
-        const int nb = make_geometry(p->nx, p->ny, kMinRows, strip_out_for(K)).nblocks;
+        const int out = K == 1 ? single_strip_out(p->flags) : kstep_strip_out(K, p->flags);
+        const int nb = make_geometry(p->nx, p->ny, kMinRows, out).nblocks;
         if (nb > cap) cap = nb;
     }
     L.part_capacity = cap;
@@ -157,8 +158,8 @@ int enqueue_steps(sw2d_ctx* h, int32_t nsteps, hipEvent_t* ev, double* total_ms)
         FoldPartial* part = h->part + (size_t)pending * h->part_capacity;
         if (ev) SW2D_HIP(hipEventRecord(ev[2 * passes], h->stream));
         if (k >= 2)
-            SW2D_HIP(launch_stepk(k, src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part, h->part_capacity,
-                                  g, h->coef, h->stream));
+            SW2D_HIP(launch_stepk(k, (int)h->p.flags, src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part,
+                                  h->part_capacity, g, h->coef, h->stream));
         else
             SW2D_HIP(launch_step((int)h->p.flags, src[0], src[1], src[2], h->hp, dst[0], dst[1], dst[2], part, g, h->coef,
                                  h->stream));
@@ -234,7 +235,7 @@ int sw2d_create(const sw2d_params* p, const float* d_H, const uint8_t* d_mask, f
     h->part_capacity = L.part_capacity;
     h->geo = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny), single_strip_out(p->flags));
     for (int K = 2; K <= kMaxStepsPerPass; ++K)
-        h->geok[K] = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny), strip_out_for(K));
+        h->geok[K] = make_geometry(p->nx, p->ny, default_rows(p->nx, p->ny), kstep_strip_out(K, p->flags));
     h->steps_per_pass = 1;
     h->coef = make_coef(p);
     h->step = 0;
@@ -336,12 +337,13 @@ int sw2d_set_band_rows(sw2d_t h, int32_t rows) {
 int sw2d_set_time_blocking(sw2d_t h, int32_t steps_per_pass, int32_t rows) {
     if (!h) return SW2D_ESTATE;
     if (steps_per_pass < 1 || steps_per_pass > kMaxStepsPerPass) return SW2D_EINVAL;
-    if (steps_per_pass >= 2 && h->p.flags != 0) return SW2D_EINVAL;  // variants step one at a time
+    // filter_uv and advection reach further per step: they step one at a time
+    if (steps_per_pass >= 2 && !kstep_variant_ok(h->p.flags)) return SW2D_EINVAL;
     if (steps_per_pass >= 2) {
         if (rows < kMinRows || rows > h->p.ny) return SW2D_EINVAL;
         // the same band height for the shorter passes that finish a step count
         for (int K = 2; K <= kMaxStepsPerPass; ++K)
-            h->geok[K] = make_geometry(h->p.nx, h->p.ny, rows, strip_out_for(K));
+            h->geok[K] = make_geometry(h->p.nx, h->p.ny, rows, kstep_strip_out(K, h->p.flags));
     }
     h->steps_per_pass = steps_per_pass;
     return SW2D_OK;

@@ -158,8 +158,9 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
 }
 
 // K steps per pass over HBM (temporal blocking): strips of 64 - 4K owned columns, bands
-// with a 2K-row halo; the intermediate states stay in registers.
-template <int K>
+// with a 2K-row halo; the intermediate states stay in registers. kVar: plain, friction or
+// wetting and drying.
+template <int K, int kVar = 0>
 __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
     const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
     const float* __restrict__ hp, float* __restrict__ eta_o, float* __restrict__ u_o,
@@ -190,10 +191,12 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
     if (strip < geo.strips) {
 #if SW2D_ZIGZAG
         if (band & 1)
-            marchK<K, false>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k, F);
+            marchK<K, false, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k,
+                                   F);
         else
 #endif
-            marchK<K, true>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k, F);
+            marchK<K, true, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k,
+                                  F);
     }
 #pragma unroll
     for (int s = 0; s < K; ++s) {
@@ -386,10 +389,27 @@ hipError_t launch_step(int kvar, const float* eta, const float* u, const float* 
     return hipGetLastError();
 }
 
-hipError_t launch_stepk(int K, const float* eta, const float* u, const float* v, const float* hp,
+hipError_t launch_stepk(int K, int kvar, const float* eta, const float* u, const float* v, const float* hp,
                         float* eta_o, float* u_o, float* v_o, FoldPartial* part, int stride,
                         const StepGeometry& geo, const StepCoef& k, hipStream_t s) {
     const dim3 grid(geo.nblocks), block(kGroupThreads);
+    if (kvar != 0) {
+        // friction and wetting/drying: the one-column pipeline of their single-step kernel
+#define SW2D_VARK_CASE(KK, V)                                                                                    \
+    if (K == KK && kvar == V) {                                                                                 \
+        hipLaunchKernelGGL((sw2d_stepk_kernel<KK, V>), grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part,  \
+                           stride, geo, k);                                                                     \
+        return hipGetLastError();                                                                               \
+    }
+        SW2D_VARK_CASE(2, kVarFriction)
+        SW2D_VARK_CASE(3, kVarFriction)
+        SW2D_VARK_CASE(4, kVarFriction)
+        SW2D_VARK_CASE(2, kVarWetDry)
+        SW2D_VARK_CASE(3, kVarWetDry)
+        SW2D_VARK_CASE(4, kVarWetDry)
+#undef SW2D_VARK_CASE
+        return hipErrorInvalidValue;
+    }
 #if SW2D_PAIR_COLUMNS
     const bool wide = (geo.nx % 2) == 0;
 #define SW2D_PAIR_CASE(KK)                                                                                         \

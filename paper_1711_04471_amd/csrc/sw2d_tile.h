@@ -619,8 +619,9 @@ __device__ __forceinline__ void march_adv(const float* __restrict__ eta, const f
 // produced, so the intermediate states never leave the registers. Each step's stencil
 // reaches two more columns into the garbage of the strip edges, so owned lanes shrink to
 // 2K .. 63-2K, and bands need a 2K-row halo; the folds of every step are taken over the
-// owned cells.
-template <int K, bool kNorth>
+// owned cells. kVar: the plain model, bottom friction or wetting and drying (variants whose
+// stencil reaches no further than the plain step's).
+template <int K, bool kNorth, int kVar = 0>
 __device__ __forceinline__ void marchK(const float* __restrict__ eta, const float* __restrict__ u,
                                        const float* __restrict__ v, const float* __restrict__ hp,
                                        float* __restrict__ eta_o, float* __restrict__ u_o,
@@ -632,7 +633,8 @@ __device__ __forceinline__ void marchK(const float* __restrict__ eta, const floa
     RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
     const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, step, n_rows);
-    Stage<kNorth> S[K];
+    static_assert(kVar == 0 || kVar == kVarFriction || kVar == kVarWetDry, "variant without K-step passes");
+    Stage<kNorth, kVar> S[K];
     int i = 0;
     // Priming: stage s starts at row 4s (march order) and has valid output from row 4(s+1).
     for (; i < 4 * K; ++i) {

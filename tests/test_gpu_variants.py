@@ -98,12 +98,34 @@ def test_variant_keeps_lake_at_rest(flags):
     assert np.array_equal(e, c.eta) and not u.any() and not v.any()
 
 
-def test_variant_handles_refuse_multi_step_passes():
+@pytest.mark.parametrize("flags", [FILTER_UV, ADVECTION, FRICTION | FILTER_UV, ADVECTION | FRICTION])
+def test_variant_handles_refuse_multi_step_passes(flags):
+    """The velocity filter and advection reach further per step than the K-step pass allows."""
     from paper_1711_04471_amd._lib import Sw2dError
     c = inputs.small_basin(64, 64, seed=2, steps=5)
-    with Sw2d.from_case(c, flags=FILTER_UV, cd=0.0) as sim:
+    with Sw2d.from_case(c, flags=flags, cd=0.0) as sim:
         with pytest.raises(Sw2dError):
             sim.set_time_blocking(3, rows=32)
         sim.step(2)
         with pytest.raises(Sw2dError):
             sim.step_unfused(1)
+
+
+@pytest.mark.parametrize("spp", [2, 3, 4])
+@pytest.mark.parametrize("shape,nsteps", [((130, 257), 23), ((301, 97), 17), ((61, 200), 9)])
+def test_friction_k_steps_per_pass_equal_single_steps(shape, nsteps, spp):
+    """Bottom friction at K steps per pass: every state bit equals single steps (which the
+    oracle pins above), the folds agree up to summation order."""
+    nx, ny = shape
+    c = _stirred(inputs.small_basin(nx, ny, seed=nx + 2 * ny, steps=nsteps), seed=nx)
+    e1, u1, v1, r1 = _gpu(c, FRICTION, nsteps)
+    for rows in (8, 40):
+        _say(f"friction {nx}x{ny} K={spp} rows={rows}")
+        with Sw2d.from_case(c, flags=FRICTION, cd=CD) as sim:
+            sim.set_time_blocking(spp, rows=min(rows, ny))
+            sim.step(nsteps)
+            red = sim.reduce(nsteps)
+            e, u, v = sim.state_numpy()
+        assert np.array_equal(e, e1) and np.array_equal(u, u1) and np.array_equal(v, v1), (shape, spp, rows)
+        np.testing.assert_allclose(red["vol_disp"], r1["vol_disp"], rtol=1e-12, atol=1e-9 * c.dx * c.dy)
+        assert np.array_equal(red["max_abs_u"], r1["max_abs_u"]) and np.array_equal(red["max_abs_v"], r1["max_abs_v"])

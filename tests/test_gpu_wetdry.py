@@ -16,7 +16,7 @@ flooding and drying tens to hundreds of cells.
 Bar: eta, u, v within 1e-5 relative L2; land and inactive faces exactly 0; folds within
 1e-5; the final wet set equal away from the threshold; bitwise independence of the band
 height; a lake at rest over emerging ground bitwise still; with every cell deep, bitwise
-the plain step.
+the plain step; at K steps per pass, bitwise the single steps.
 """
 import numpy as np
 import pytest
@@ -143,12 +143,27 @@ def test_wetdry_is_the_plain_step_while_every_cell_is_deep():
         assert np.array_equal(x, y)
 
 
-def test_wetdry_handle_refuses_multi_step_passes():
+@pytest.mark.parametrize("spp", [2, 3, 4])
+def test_wetdry_k_steps_per_pass_equal_single_steps(spp):
+    """Wetting and drying at K steps per pass, on a shore basin that floods and dries cells:
+    every state bit equals single steps, the folds agree up to summation order."""
+    c = inputs.shore_basin(257, 190, seed=54, steps=100)
+    ref = _gpu(c, 100)
+    for rows in (8, 32):
+        _say(f"wetdry K={spp} rows={rows}")
+        with Sw2d.from_case(c, flags=WETDRY, hmin=HMIN) as sim:
+            sim.set_time_blocking(spp, rows=rows)
+            sim.step(100)
+            red = sim.reduce(100)
+            e, u, v = sim.state_numpy()
+        for x, y in zip((e, u, v), ref[:3]):
+            assert np.array_equal(x, y), (spp, rows)
+        np.testing.assert_allclose(red["vol_disp"], ref[3]["vol_disp"], rtol=1e-12, atol=1e-9 * c.dx * c.dy)
+        assert np.array_equal(red["max_abs_u"], ref[3]["max_abs_u"])
+
+
+def test_wetdry_takes_no_other_flag():
     from paper_1711_04471_amd._lib import Sw2dError
     c = inputs.shore_basin(64, 64, seed=2, steps=5)
-    with Sw2d.from_case(c, flags=WETDRY, hmin=HMIN) as sim:
-        with pytest.raises(Sw2dError):
-            sim.set_time_blocking(2, rows=32)
-        sim.step(2)
     with pytest.raises(Sw2dError):
         Sw2d.from_case(c, flags=WETDRY | FILTER_UV, hmin=HMIN)
