@@ -316,8 +316,8 @@ def variants_leg(case, steps, log):
     """The single-step kernel with each model variant (bottom friction, velocity filter,
     advection, all three, wetting and drying) on the same basin: same 28 B per cell-step,
     more arithmetic per cell. The kernels take every decision with selects, not branches,
-    so their time does not depend on how many cells are dry. Friction and wetting/drying
-    are also timed at several steps per pass."""
+    so their time does not depend on how many cells are dry. Friction, the velocity filter
+    and wetting/drying are also timed at several steps per pass."""
     import torch
 
     from paper_1711_04471_amd.sw2d import ADVECTION, FILTER_UV, FRICTION, WETDRY, Sw2d
@@ -336,7 +336,7 @@ def variants_leg(case, steps, log):
         out[name] = {"ms_per_step": round(ms, 5), "value": round(cells / ms / 1e3, 1),
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     # the variants that also take several steps per pass (one column per lane), at their best
-    for name, flags in (("friction", FRICTION), ("wetdry", WETDRY)):
+    for name, flags in (("friction", FRICTION), ("filter_uv", FILTER_UV), ("wetdry", WETDRY)):
         K, rows = VARIANT_PASS[name]
         with Sw2d.from_case(case, flags=flags, cd=0.0025, hmin=0.0625) as sim:
             sim.set_time_blocking(K, rows=rows)
@@ -352,7 +352,7 @@ def variants_leg(case, steps, log):
 
 # steps per pass and band rows of the variants' K-step passes (best of K = 2..4 x rows 16..64
 # on the 8192^2 basin)
-VARIANT_PASS = {"friction": (2, 32), "wetdry": (3, 32)}
+VARIANT_PASS = {"friction": (2, 32), "filter_uv": (2, 16), "wetdry": (3, 32)}
 
 
 SOR_BYTES_PER_CELL_ITER = 16  # read the other colour, own colour and own f; write own colour

@@ -78,10 +78,9 @@ enum {
  *                  holds: H is the depth below the datum, which may sit above the still-water
  *                  level, so ground that can flood is a water cell whose surface starts at
  *                  eta = -H (zero total depth). Taken alone (no other flag).
- * A handle with SW2D_FILTER_UV or SW2D_ADVECTION steps one step per pass
- * (sw2d_set_time_blocking refuses K > 1: their stencils reach further per step); the plain
- * model, SW2D_FRICTION alone and SW2D_WETDRY may take K steps per pass. The batched and
- * unfused paths take flags = 0 only. */
+ * A handle with SW2D_ADVECTION steps one step per pass (sw2d_set_time_blocking refuses
+ * K > 1: its upwind differences reach one face further per step); every other combination
+ * may take K steps per pass. The batched and unfused paths take flags = 0 only. */
 #define SW2D_FRICTION 1u
 #define SW2D_FILTER_UV 2u
 #define SW2D_ADVECTION 4u
@@ -166,7 +165,7 @@ int32_t sw2d_band_rows(sw2d_t h);
  * one shorter pass), with its own band height rows in [8, ny]; 1 (the default) restores one
  * step per pass. The state and folds are the same as with single steps (the state bit for
  * bit, the folds up to the order of their sums). SW2D_EINVAL for K or rows out of range, or
- * K > 1 on a handle with SW2D_FILTER_UV or SW2D_ADVECTION. */
+ * K > 1 on a handle with SW2D_ADVECTION. */
 int sw2d_set_time_blocking(sw2d_t h, int32_t steps_per_pass, int32_t rows);
 int32_t sw2d_time_blocking(sw2d_t h);
 

@@ -69,10 +69,11 @@ constexpr int kAdvHaloW = 3;
 constexpr int kAdvStripOut = kWave - kAdvHaloW - kHalo;
 constexpr int single_strip_out(uint32_t flags) { return (flags & kVarAdvection) ? kAdvStripOut : kStripOut; }
 // Owned columns of a strip for K >= 2 steps per pass: the two-column pass for the plain
-// model, the one-column pass for the variants that have one (friction, wetting and drying).
+// model, the one-column pass for the variants that have one (all but advection).
 constexpr int kstep_strip_out(int K, uint32_t flags) { return flags ? kWave - 4 * K : strip_out_for(K); }
-// Variants that may advance several steps per pass.
-constexpr bool kstep_variant_ok(uint32_t flags) { return flags == 0 || flags == kVarFriction || flags == kVarWetDry; }
+// Variants that may advance several steps per pass: those whose step reaches no further than
+// the plain step's two cells (advection reads one more face upstream).
+constexpr bool kstep_variant_ok(uint32_t flags) { return (flags & kVarAdvection) == 0; }
 
 enum : uint32_t {
     kWetBorder = 1u,
@@ -106,7 +107,7 @@ hipError_t launch_step(int kvar, const float* eta, const float* u, const float* 
                        float* eta_o, float* u_o, float* v_o, FoldPartial* part,
                        const StepGeometry& geo, const StepCoef& k, hipStream_t s);
 // K = 2..4 steps in one pass (geometry from make_geometry(..., kstep_strip_out(K, flags))),
-// kvar 0, kVarFriction or kVarWetDry; the partials of step s of the pass go to
+// kvar 0 or a variant without advection; the partials of step s of the pass go to
 // part[s * stride + 0..nblocks).
 hipError_t launch_stepk(int K, int kvar, const float* eta, const float* u, const float* v, const float* hp,
                         float* eta_o, float* u_o, float* v_o, FoldPartial* part, int stride,

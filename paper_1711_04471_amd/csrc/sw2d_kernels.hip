@@ -158,8 +158,8 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
 }
 
 // K steps per pass over HBM (temporal blocking): strips of 64 - 4K owned columns, bands
-// with a 2K-row halo; the intermediate states stay in registers. kVar: plain, friction or
-// wetting and drying.
+// with a 2K-row halo; the intermediate states stay in registers. kVar: plain or a variant
+// without advection.
 template <int K, int kVar = 0>
 __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
     const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
@@ -394,16 +394,22 @@ hipError_t launch_stepk(int K, int kvar, const float* eta, const float* u, const
                         const StepGeometry& geo, const StepCoef& k, hipStream_t s) {
     const dim3 grid(geo.nblocks), block(kGroupThreads);
     if (kvar != 0) {
-        // friction and wetting/drying: the one-column pipeline of their single-step kernel
+        // the variants without advection: the one-column pipeline of their single-step kernel
 #define SW2D_VARK_CASE(KK, V)                                                                                    \
-    if (K == KK && kvar == V) {                                                                                 \
-        hipLaunchKernelGGL((sw2d_stepk_kernel<KK, V>), grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part,  \
+    if (K == (KK) && kvar == (V)) {                                                                             \
+        hipLaunchKernelGGL((sw2d_stepk_kernel<KK, (V)>), grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, \
                            stride, geo, k);                                                                     \
         return hipGetLastError();                                                                               \
     }
         SW2D_VARK_CASE(2, kVarFriction)
         SW2D_VARK_CASE(3, kVarFriction)
         SW2D_VARK_CASE(4, kVarFriction)
+        SW2D_VARK_CASE(2, kVarFilterUV)
+        SW2D_VARK_CASE(3, kVarFilterUV)
+        SW2D_VARK_CASE(4, kVarFilterUV)
+        SW2D_VARK_CASE(2, kVarFriction | kVarFilterUV)
+        SW2D_VARK_CASE(3, kVarFriction | kVarFilterUV)
+        SW2D_VARK_CASE(4, kVarFriction | kVarFilterUV)
         SW2D_VARK_CASE(2, kVarWetDry)
         SW2D_VARK_CASE(3, kVarWetDry)
         SW2D_VARK_CASE(4, kVarWetDry)

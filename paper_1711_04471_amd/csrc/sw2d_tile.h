@@ -619,8 +619,8 @@ __device__ __forceinline__ void march_adv(const float* __restrict__ eta, const f
 // produced, so the intermediate states never leave the registers. Each step's stencil
 // reaches two more columns into the garbage of the strip edges, so owned lanes shrink to
 // 2K .. 63-2K, and bands need a 2K-row halo; the folds of every step are taken over the
-// owned cells. kVar: the plain model, bottom friction or wetting and drying (variants whose
-// stencil reaches no further than the plain step's).
+// owned cells. kVar: the plain model or a variant whose step reaches no further than the
+// plain step's (friction, the velocity filter, both, or wetting and drying; not advection).
 template <int K, bool kNorth, int kVar = 0>
 __device__ __forceinline__ void marchK(const float* __restrict__ eta, const float* __restrict__ u,
                                        const float* __restrict__ v, const float* __restrict__ hp,
@@ -633,7 +633,7 @@ __device__ __forceinline__ void marchK(const float* __restrict__ eta, const floa
     RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
     const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, step, n_rows);
-    static_assert(kVar == 0 || kVar == kVarFriction || kVar == kVarWetDry, "variant without K-step passes");
+    static_assert((kVar & kVarAdvection) == 0, "advection reaches too far for K-step passes");
     Stage<kNorth, kVar> S[K];
     int i = 0;
     // Priming: stage s starts at row 4s (march order) and has valid output from row 4(s+1).

@@ -98,9 +98,9 @@ def test_variant_keeps_lake_at_rest(flags):
     assert np.array_equal(e, c.eta) and not u.any() and not v.any()
 
 
-@pytest.mark.parametrize("flags", [FILTER_UV, ADVECTION, FRICTION | FILTER_UV, ADVECTION | FRICTION])
+@pytest.mark.parametrize("flags", [ADVECTION, ADVECTION | FRICTION, ADVECTION | FILTER_UV])
 def test_variant_handles_refuse_multi_step_passes(flags):
-    """The velocity filter and advection reach further per step than the K-step pass allows."""
+    """Advection reaches one face further upstream per step than the K-step pass allows."""
     from paper_1711_04471_amd._lib import Sw2dError
     c = inputs.small_basin(64, 64, seed=2, steps=5)
     with Sw2d.from_case(c, flags=flags, cd=0.0) as sim:
@@ -111,17 +111,18 @@ def test_variant_handles_refuse_multi_step_passes(flags):
             sim.step_unfused(1)
 
 
+@pytest.mark.parametrize("flags", [FRICTION, FILTER_UV, FRICTION | FILTER_UV])
 @pytest.mark.parametrize("spp", [2, 3, 4])
 @pytest.mark.parametrize("shape,nsteps", [((130, 257), 23), ((301, 97), 17), ((61, 200), 9)])
-def test_friction_k_steps_per_pass_equal_single_steps(shape, nsteps, spp):
-    """Bottom friction at K steps per pass: every state bit equals single steps (which the
-    oracle pins above), the folds agree up to summation order."""
+def test_variant_k_steps_per_pass_equal_single_steps(shape, nsteps, spp, flags):
+    """Friction and the velocity filter at K steps per pass: every state bit equals single
+    steps (which the oracle pins above), the folds agree up to summation order."""
     nx, ny = shape
     c = _stirred(inputs.small_basin(nx, ny, seed=nx + 2 * ny, steps=nsteps), seed=nx)
-    e1, u1, v1, r1 = _gpu(c, FRICTION, nsteps)
+    e1, u1, v1, r1 = _gpu(c, flags, nsteps)
     for rows in (8, 40):
-        _say(f"friction {nx}x{ny} K={spp} rows={rows}")
-        with Sw2d.from_case(c, flags=FRICTION, cd=CD) as sim:
+        _say(f"flags {flags} {nx}x{ny} K={spp} rows={rows}")
+        with Sw2d.from_case(c, flags=flags, cd=CD) as sim:
             sim.set_time_blocking(spp, rows=min(rows, ny))
             sim.step(nsteps)
             red = sim.reduce(nsteps)
