@@ -415,6 +415,10 @@ def sor_leg(args, log):
 
 def main():
     args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(row-strip sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
     if args.copy_probe:
         copy_probe()
         return
@@ -428,10 +432,6 @@ def main():
     if args.only_sor:
         print(json.dumps({"sor": sor_leg(args, log)}), flush=True)
         return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(row-strip sharding is a design note only); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
     import torch
 
     from paper_1711_04471_amd import inputs
