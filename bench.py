@@ -226,7 +226,10 @@ def batched_leg(steps, warmup, log):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(cells * BYTES_PER_CELL_STEP / K / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "basis": f"whole persistent sequence (HIP events), 28 B per cell and pass of {K} steps"},
-        "grid_workgroups": grid, "band_rows_by_class": sorted(set(rows)),
+        "grid_workgroups": grid,
+        "band_rows_by_class": {"%d-%d" % (lo, hi - 1): sorted({r for c, r in zip(cases, rows)
+                                                              if autotune.size_class(int(c.nx)) == (lo, hi)})
+                               for lo, hi in autotune.CLASSES},
         "finite_folds": bool(np.isfinite(red["vol_total"]).all()),
     }
 
