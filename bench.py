@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--only-surrogate", action="store_true")
     ap.add_argument("--surrogate-runs", type=int, default=20)
     ap.add_argument("--surrogate-pairs", type=int, default=100)
-    ap.add_argument("--surrogate-epochs", type=int, default=6)
+    ap.add_argument("--surrogate-epochs", type=int, default=18)
     ap.add_argument("--surrogate-fine", type=int, default=4096)
     ap.add_argument("--surrogate-tests", type=int, default=3)
     ap.add_argument("--damping", type=float, default=0.5)
