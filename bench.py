@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # (10), y-face likewise (8), Shapiro filter (9), folds (3), water flags (3); an FMA counts
 # as 2, compares and maxima as 1, selects and lane exchanges not at all.
 FLOP_PER_CELL_STEP = 33
-# FP32 vector peak without packed two-wide instructions (this build emits none):
+# FP32 vector peak without packed two-wide instructions (the kernels are compiled without them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -419,7 +419,7 @@ def sor_leg(args, log):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(row-strip sharding is a design note only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
