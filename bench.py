@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--surrogate-tests", type=int, default=3)
     ap.add_argument("--damping", type=float, default=0.5)
     ap.add_argument("--no-variants", action="store_true", help="skip the model-variant leg")
+    ap.add_argument("--only-basin2048", action="store_true",
+                    help="only the 2048^2 basin (1000 steps at 1 and 4 steps per pass)")
     ap.add_argument("--no-sor", action="store_true", help="skip the SOR pressure-solver leg")
     ap.add_argument("--only-sor", action="store_true")
     ap.add_argument("--sor-solves", type=int, default=10)
@@ -353,6 +355,41 @@ def variants_leg(case, steps, log):
             "unit": "Mcell-steps/s", **out}
 
 
+def basin2048_leg(steps, log):
+    """The 2048^2 basin (1000 steps with the folds of every step) at one and at four steps
+    per pass. Its working set (eta, u, v twice and H: 117 MB) fits the 256 MB Infinity Cache,
+    so this rate is not bound by HBM."""
+    import torch
+
+    from paper_1711_04471_amd import inputs
+    from paper_1711_04471_amd.sw2d import Sw2d
+
+    case = inputs.basin_2048()
+    cells = case.nx * case.ny
+    out = {"workload": f"{case.name}: {case.nx}x{case.ny} cells incl. land border, dx={case.dx:g} m, "
+                       f"dt={case.dt:.4f} s, seed 2, 8 bumps, {steps} steps, folds every step",
+           "unit": "Mcell-steps/s"}
+    for spp in (1, 4):
+        rows = TUNED_ROWS[("basin_2048", spp)]
+        with Sw2d.from_case(case) as sim:
+            if spp == 1:
+                sim.band_rows = rows
+            else:
+                sim.set_time_blocking(spp, rows=rows)
+            sim.step(4 * spp)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            red = sim.reduce(1)
+        out[f"{spp}_per_pass"] = {"ms_per_step": round(wall / steps * 1e3, 5),
+                                  "value": round(cells * steps / wall / 1e6, 1), "band_rows": rows,
+                                  "finite_folds": bool(np.isfinite(red["vol_total"]).all())}
+    log(f"basin_2048: {out}")
+    return out
+
+
 # steps per pass and band rows of the variants' K-step passes (best of K = 2..4 x rows 16..64
 # on the 8192^2 basin)
 VARIANT_PASS = {"friction": (2, 32), "filter_uv": (2, 16), "wetdry": (3, 32)}
@@ -434,6 +471,9 @@ def main():
         return
     if args.only_sor:
         print(json.dumps({"sor": sor_leg(args, log)}), flush=True)
+        return
+    if args.only_basin2048:
+        print(json.dumps({"basin_2048": basin2048_leg(1000, log)}), flush=True)
         return
     import torch
 

@@ -9,7 +9,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("extra", [[], ["--only-batched"], ["--only-surrogate"], ["--only-sor"], ["--copy-probe"]])
+@pytest.mark.parametrize("extra", [[], ["--only-batched"], ["--only-surrogate"], ["--only-sor"], ["--only-basin2048"],
+                                   ["--copy-probe"]])
 def test_more_than_one_gpu_is_refused(extra):
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", *extra],
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
