@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--damping", type=float, default=0.5)
     ap.add_argument("--no-variants", action="store_true", help="skip the model-variant leg")
     ap.add_argument("--only-basin2048", action="store_true",
-                    help="only the 2048^2 basin (1000 steps at 1 and 4 steps per pass)")
+                    help="only the 2048^2 basin (1000 steps at 1, 3 and 4 steps per pass)")
     ap.add_argument("--no-sor", action="store_true", help="skip the SOR pressure-solver leg")
     ap.add_argument("--only-sor", action="store_true")
     ap.add_argument("--sor-solves", type=int, default=10)
@@ -101,7 +101,7 @@ def copy_probe(quiet=False):
 # throughput is a sawtooth in the band height, from how the last workgroups of a launch fill
 # the GPU)
 TUNED_ROWS = {("basin_8192", 1): 16, ("basin_8192", 2): 16, ("basin_8192", 3): 64, ("basin_8192", 4): 104,
-              ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 16}
+              ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 24}
 
 
 # the plain fine model the surrogate is compared with (and judged by): steps per pass, rows
@@ -356,7 +356,7 @@ def variants_leg(case, steps, log):
 
 
 def basin2048_leg(steps, log):
-    """The 2048^2 basin (1000 steps with the folds of every step) at one and at four steps
+    """The 2048^2 basin (1000 steps with the folds of every step) at one, three and four steps
     per pass. Its working set (eta, u, v twice and H: 117 MB) fits the 256 MB Infinity Cache,
     so this rate is not bound by HBM."""
     import torch
@@ -369,7 +369,7 @@ def basin2048_leg(steps, log):
     out = {"workload": f"{case.name}: {case.nx}x{case.ny} cells incl. land border, dx={case.dx:g} m, "
                        f"dt={case.dt:.4f} s, seed 2, 8 bumps, {steps} steps, folds every step",
            "unit": "Mcell-steps/s"}
-    for spp in (1, 4):
+    for spp in (1, 3, 4):
         rows = TUNED_ROWS[("basin_2048", spp)]
         with Sw2d.from_case(case) as sim:
             if spp == 1:
