@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--surrogate-fine", type=int, default=4096)
     ap.add_argument("--surrogate-tests", type=int, default=3)
     ap.add_argument("--damping", type=float, default=0.5)
+    ap.add_argument("--surrogate-every", type=int, default=5,
+                    help="run the network before every m-th coarse step (trained m coarse steps ahead)")
     ap.add_argument("--no-variants", action="store_true", help="skip the model-variant leg")
     ap.add_argument("--only-basin2048", action="store_true",
                     help="only the 2048^2 basin (1000 steps at 1, 3 and 4 steps per pass)")
@@ -248,7 +250,8 @@ def surrogate_leg(args, log):
 
     n = args.surrogate_fine
     t0 = time.perf_counter()
-    ds = S.make_dataset([50000 + k for k in range(args.surrogate_runs)], n=n, pairs_per_run=args.surrogate_pairs)
+    ds = S.make_dataset([50000 + k for k in range(args.surrogate_runs)], n=n, pairs_per_run=args.surrogate_pairs,
+                        lead=4 * args.surrogate_every)
     gen_s = time.perf_counter() - t0
     log(f"surrogate dataset {tuple(ds.inputs.shape)} in {gen_s:.1f} s")
     net = S.ConvNet(seed=1)
@@ -280,7 +283,7 @@ def surrogate_leg(args, log):
             t_plain = plain.step_timed(4 * n_coarse) * 4 * n_coarse * 1e-3
         with fine_sim(case) as judge_sim:
             r_cnn = S.rollout(net, case, n_coarse=n_coarse, judge_every=judge, threshold=thr,
-                              damping=args.damping, fine=judge_sim)
+                              damping=args.damping, fine=judge_sim, correct_every=args.surrogate_every)
         with fine_sim(case) as judge_sim:
             r_crs = S.rollout(None, case, n_coarse=n_coarse, judge_every=judge, threshold=thr, fine=judge_sim)
         seg_plain = t_plain / (n_coarse // judge)
@@ -301,7 +304,8 @@ def surrogate_leg(args, log):
         "workload": f"surrogate_{n}: fine {n}^2 (4-cell border, dx=500 m) -> coarse {n // 4}^2, CNN 5-32-32-32-3 "
                     f"3x3 BF16/FP32-acc, {samples} training pairs from {args.surrogate_runs} plain runs, "
                     f"{args.surrogate_epochs} epochs; rollout {n_coarse} coarse steps, judge every {judge}, "
-                    f"threshold {thr} m, damping {args.damping}",
+                    f"threshold {thr} m, damping {args.damping}, network before every "
+                    f"{args.surrogate_every} coarse step(s)",
         "value_fine_equivalent": round(cells * 4 * n_coarse * len(per) / t_chg / 1e6, 1),
         "unit": "Mcell-steps/s (fine cells x fine steps / wall time incl. fallbacks)",
         "plain_config": f"{SURROGATE_PASS[0]} steps per pass, {SURROGATE_PASS[1]}-row bands",

@@ -264,7 +264,10 @@ class Dataset:
 
 def make_dataset(seeds, n=4096, pairs_per_run=100, every=20, lead=4, device="cuda", log=None) -> Dataset:
     """Snapshot pairs from plain fine runs: at fine steps 0, every, 2 every, ... the input is
-    R(s_t) and the target R(s_{t+lead}) - C(R(s_t)) (one coarse step of 4 dt)."""
+    R(s_t) and the target R(s_{t+lead}) - C^m(R(s_t)), m = lead / 4 coarse steps of 4 dt (one
+    by default)."""
+    if lead <= 0 or lead % 4 or lead > every:
+        raise ValueError("lead must be a positive multiple of 4 fine steps, at most every")
     dev = torch.device(device)
     lib = _lib.load()
     t0 = time.perf_counter()
@@ -291,7 +294,7 @@ def make_dataset(seeds, n=4096, pairs_per_run=100, every=20, lead=4, device="cud
                 for c, f in enumerate((co.eta, co.u, co.v)):
                     ins[c, k].copy_(f)
                 co.sim.set_state(co.eta, co.u, co.v, step=0)
-                co.sim.step(1)
+                co.sim.step(lead // 4)
                 ce, cu, cv = co.sim.state()
                 fine.step(lead)
                 co.restrict(fine, out=ahead)
@@ -432,12 +435,16 @@ class RolloutResult:
 
 
 def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1e-3, device="cuda",
-            fine: Sw2d | None = None, damping=0.5):
+            fine: Sw2d | None = None, damping=0.5, correct_every=1):
     """Advance the surrogate n_coarse coarse steps from the restricted initial state of
     `case`; the fine model judges every judge_every steps and takes over above threshold.
     With net None the coarse model runs alone (the method without the learned part).
     The correction is applied scaled by `damping` (a one-step-trained correction applied at
-    full strength every step amplifies its own errors over long rollouts)."""
+    full strength every step amplifies its own errors over long rollouts). correct_every = m:
+    the network runs on the state before every m-th coarse step and its output corrects the
+    state m steps later (a network trained with lead = 4 m fine steps)."""
+    if correct_every < 1 or judge_every % correct_every:
+        raise ValueError("correct_every must divide judge_every")
     dev = torch.device(device)
     lib = _lib.load()
     own_fine = fine is None
@@ -456,10 +463,18 @@ def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1
         t0 = time.perf_counter()
         if net is None:
             co.sim.step(judge_every)
-        else:
+        elif correct_every == 1:
             # the network sees the state before each coarse step, as in training; one kernel
             # runs all four layers and its output corrects the stepped state
             net.advance(co.sim, judge_every, co.H, co.mask, mp, sp, tp)
+        else:
+            for _ in range(judge_every // correct_every):
+                e, u, v = co.sim.state()
+                out = net.forward_fused(e, u, v, co.H, co.mask, co.sim.ny, co.sim.nx, mp, sp)
+                co.sim.step(correct_every)
+                e, u, v = co.sim.state()
+                check(lib.sw2d_apply_correction(_p(e), _p(u), _p(v), _p(out), _p(co.mask), co.sim.nx, co.sim.ny,
+                                                tp, s), "sw2d_apply_correction")
         torch.cuda.synchronize(dev)
         t1 = time.perf_counter()
         fine.step(4 * judge_every)

@@ -164,6 +164,29 @@ def test_trained_network_gains_over_coarse_only(trained):
     assert np.mean(ratios) < 0.92 and max(ratios) < 1.05, ratios
 
 
+@pytest.fixture(scope="module")
+def trained_every5():
+    """A network trained on targets five coarse steps ahead (lead = 20 fine steps)."""
+    ds = S.make_dataset([50000 + k for k in range(12)], n=FINE, pairs_per_run=100, lead=20)
+    net = S.ConvNet(seed=1)
+    S.Trainer(net, ds, batch=4, noise=0.05).fit(epochs=24, lr=2e-3)
+    return net
+
+
+def test_network_every_fifth_step_gains_over_coarse_only(trained_every5):
+    """The network run before every fifth coarse step, its output correcting the state five
+    steps later: eta RMSE after 20 coarse steps on held-out basins against the coarse model
+    alone, as for the every-step network."""
+    ratios = []
+    for seed in (50200, 50201, 50202, 50203):
+        case = S.fine_basin(seed, FINE)
+        base = S.rollout(None, case, n_coarse=20, judge_every=20, threshold=1e9).rmse[0]
+        cnn = S.rollout(trained_every5, case, n_coarse=20, judge_every=20, threshold=1e9, correct_every=5).rmse[0]
+        ratios.append(cnn / base)
+    print(json.dumps({"rmse_ratio_cnn_every5_over_coarse": ratios}), flush=True)
+    assert np.mean(ratios) < 0.92 and max(ratios) < 1.05, ratios
+
+
 def test_advance_equals_the_layer_by_layer_steps(trained):
     """The one-call corrected steps (one kernel for the network, the coarse step, the
     correction) give bitwise the state of the layer-by-layer path step by step."""
