@@ -5,8 +5,9 @@ fused step on the coarse grid (4 dx, 4 dt, so the Courant number is unchanged) a
 correction predicted by a small convolutional network (3x3 'same' convolutions 5 -> 32 ->
 32 -> 32 -> 3, ReLU after the first three; BF16 weights and activations on the matrix
 cores, FP32 accumulation and FP32 master weights). The network learns the difference
-between the restricted fine state 4 fine steps later and one coarse step from the
-restricted fine state. The plain fine model stays the judge: every ``judge_every`` coarse
+between the restricted fine state 4m fine steps later and m coarse steps from the
+restricted fine state; in the rollout it runs before every m-th coarse step and its output
+corrects the state m steps later (m = 1: every step). The plain fine model stays the judge: every ``judge_every`` coarse
 steps it is advanced to the same time, restricted, and the RMSE of eta over coarse water
 cells is measured; above the threshold the coarse state is reset from the fine one and a
 fallback is counted.
