@@ -251,7 +251,7 @@ def surrogate_leg(args, log):
     n = args.surrogate_fine
     t0 = time.perf_counter()
     ds = S.make_dataset([50000 + k for k in range(args.surrogate_runs)], n=n, pairs_per_run=args.surrogate_pairs,
-                        lead=4 * args.surrogate_every)
+                        every=max(20, 4 * args.surrogate_every), lead=4 * args.surrogate_every)
     gen_s = time.perf_counter() - t0
     log(f"surrogate dataset {tuple(ds.inputs.shape)} in {gen_s:.1f} s")
     net = S.ConvNet(seed=1)
