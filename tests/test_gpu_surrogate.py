@@ -176,7 +176,8 @@ def trained_every5():
 def test_network_every_fifth_step_gains_over_coarse_only(trained_every5):
     """The network run before every fifth coarse step, its output correcting the state five
     steps later: eta RMSE after 20 coarse steps on held-out basins against the coarse model
-    alone, as for the every-step network."""
+    alone, as for the every-step network. Measured when this bar was set: ratios 0.62-0.86,
+    mean 0.75."""
     ratios = []
     for seed in (50200, 50201, 50202, 50203):
         case = S.fine_basin(seed, FINE)
@@ -184,7 +185,7 @@ def test_network_every_fifth_step_gains_over_coarse_only(trained_every5):
         cnn = S.rollout(trained_every5, case, n_coarse=20, judge_every=20, threshold=1e9, correct_every=5).rmse[0]
         ratios.append(cnn / base)
     print(json.dumps({"rmse_ratio_cnn_every5_over_coarse": ratios}), flush=True)
-    assert np.mean(ratios) < 0.92 and max(ratios) < 1.05, ratios
+    assert np.mean(ratios) < 0.85 and max(ratios) < 0.95, ratios
 
 
 def test_advance_equals_the_layer_by_layer_steps(trained):
