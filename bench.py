@@ -293,6 +293,7 @@ def surrogate_leg(args, log):
                     "t_surrogate_s": r_cnn.surrogate_s,
                     "t_charged_s": charged, "t_judge_s": r_cnn.judge_s, "fallbacks": r_cnn.fallbacks,
                     "fallbacks_coarse_only": r_crs.fallbacks,
+                    "t_coarse_only_charged_s": r_crs.surrogate_s + r_crs.fallbacks * seg_plain,
                     "rmse_cnn": [round(x, 6) for x in r_cnn.rmse],
                     "rmse_coarse_only": [round(x, 6) for x in r_crs.rmse]})
         log(f"surrogate seed {seed}: {per[-1]}")
@@ -314,6 +315,8 @@ def surrogate_leg(args, log):
         "speedup_vs_single_step_plain_charged": round(sum(p["t_plain_single_step_s"] for p in per) / t_chg, 3),
         "fallbacks": sum(p["fallbacks"] for p in per),
         "fallbacks_coarse_only": sum(p["fallbacks_coarse_only"] for p in per),
+        # the method without the network, charged the same way (context for what the network buys)
+        "speedup_coarse_only_charged": round(t_plain / sum(p["t_coarse_only_charged_s"] for p in per), 3),
         "judges": len(per) * (n_coarse // judge),
         "mean_rmse_cnn": float(np.nanmean([x for p in per for x in p["rmse_cnn"]])),
         "mean_rmse_coarse_only": float(np.mean([x for p in per for x in p["rmse_coarse_only"]])),
