@@ -11,7 +11,9 @@ whole-array numpy operations and no blocking or fusion:
 * ``restrict4``  - 4x4 block restriction of (eta, u, v, H, mask);
 * ``conv3x3`` / ``conv3x3_dgrad`` / ``conv3x3_wgrad`` - 'same' 3x3 cross-correlation with
   zero padding and its two gradients, derived by hand from
-  y[o, p] = b[o] + sum_c sum_(dy,dx) W[o, c, dy+1, dx+1] x[c, p + (dy, dx)];
+  y[o, p] = b[o] + sum_c sum_(dy,dx) W[o, c, dy+1, dx+1] x[c, p + (dy, dx)]; for each tap the
+  sum over channels (or, for the weight gradient, over pixels) is one library matrix
+  product (numpy.tensordot);
 * ``forward`` / ``backward`` - the 4-layer network (ReLU after layers 1-3);
 * ``masked_mse`` - mean squared error over the active entries of each output channel;
 * ``adam_step`` - Adam (Kingma & Ba, 2015) with bias correction;
@@ -86,7 +88,8 @@ def conv3x3(x, W, b):
     y = np.broadcast_to(b[:, None, None], (W.shape[0], Hh, Ww)).copy()
     for ky in range(3):
         for kx in range(3):
-            y += np.einsum("oc,chw->ohw", W[:, :, ky, kx], xp[:, ky:ky + Hh, kx:kx + Ww])
+            # the sum over input channels c of one tap: a matrix product
+            y += np.tensordot(W[:, :, ky, kx], xp[:, ky:ky + Hh, kx:kx + Ww], axes=([1], [0]))
     return y
 
 
@@ -97,7 +100,7 @@ def conv3x3_dgrad(dy, W):
     dxp = np.zeros((W.shape[1], Hh + 2, Ww + 2))
     for ky in range(3):
         for kx in range(3):
-            dxp[:, ky:ky + Hh, kx:kx + Ww] += np.einsum("oc,ohw->chw", W[:, :, ky, kx], dy)
+            dxp[:, ky:ky + Hh, kx:kx + Ww] += np.tensordot(W[:, :, ky, kx], dy, axes=([0], [0]))
     return dxp[:, 1:-1, 1:-1]
 
 
@@ -109,7 +112,7 @@ def conv3x3_wgrad(x, dy):
     dW = np.zeros((dy.shape[0], C, 3, 3))
     for ky in range(3):
         for kx in range(3):
-            dW[:, :, ky, kx] = np.einsum("ohw,chw->oc", dy, xp[:, ky:ky + Hh, kx:kx + Ww])
+            dW[:, :, ky, kx] = np.tensordot(dy, xp[:, ky:ky + Hh, kx:kx + Ww], axes=([1, 2], [1, 2]))
     return dW, dy.sum(axis=(1, 2))
 
 
