@@ -186,10 +186,12 @@ def splitmix_uniform(seed, i):
 
 
 def normalise(eta, u, v, H, mask, mean, std, noise_amp=0.0, noise_seed=0):
-    """The 5 input channels (eta, u, v, H, mask), each shifted and scaled: (x - mean) / std,
-    plus (training only) noise_amp * U on channels 0..2, U = splitmix_uniform(seed, 3 p + c)
-    for the row-major pixel index p."""
-    x = np.stack([_f64(eta), _f64(u), _f64(v), _f64(H), _f64(mask)])
+    """The 5 input channels (eta, u, v, H, water flag), each shifted and scaled:
+    (x - mean) / std, the water flag being 1 where mask is nonzero and 0 elsewhere; plus
+    (training only) noise_amp * U on channels 0..2, U = splitmix_uniform(seed, 3 p + c) for
+    the row-major pixel index p."""
+    flag = (np.asarray(mask) != 0).astype(np.float64)
+    x = np.stack([_f64(eta), _f64(u), _f64(v), _f64(H), flag])
     y = (x - _f64(mean)[:, None, None]) / _f64(std)[:, None, None]
     if noise_amp > 0.0:
         H_, W_ = y.shape[1:]

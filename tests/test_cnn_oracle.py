@@ -198,3 +198,47 @@ def test_splitmix64_published_outputs():
     assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
     u = cnn_ref.splitmix_uniform(12345, np.arange(200000))
     assert u.min() >= -1.0 and u.max() < 1.0 and abs(u.mean()) < 0.01 and abs(u.var() - 1 / 3) < 0.01
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        return json.load(f)
+
+
+def test_normalise_hand_example():
+    """Channel order, (x - mean) / std and the 0/1 water flag on a hand-worked 2 x 3 grid."""
+    g = _golden("normalise_2x3.json")
+    f = lambda k: np.array(g[k], dtype=np.float64)
+    y = cnn_ref.normalise(f("eta"), f("u"), f("v"), f("H"), np.array(g["mask"], dtype=np.uint8),
+                          f("mean"), f("std"))
+    assert y.shape == (5, 2, 3)
+    assert np.array_equal(y, f("expected"))
+
+
+def test_normalise_noise_counters():
+    """Noise goes on eta, u, v only, at SplitMix64 counter 3 p + c; pixel 0 against the
+    generator's published first outputs for seed 0, every other pixel against the pinned
+    generator at its counter."""
+    g = _golden("normalise_2x3.json")
+    f = lambda k: np.array(g[k], dtype=np.float64)
+    args = (f("eta"), f("u"), f("v"), f("H"), np.array(g["mask"], dtype=np.uint8), f("mean"), f("std"))
+    amp, seed = g["noise_amp"], g["noise_seed"]
+    clean = cnn_ref.normalise(*args)
+    noisy = cnn_ref.normalise(*args, noise_amp=amp, noise_seed=seed)
+    d = (noisy - clean) / amp
+    assert not d[3:].any()
+    published = [int(h, 16) for h in g["splitmix64_seed0_first_outputs"]]
+    for c in range(3):
+        want = (published[c] >> 40) / 2.0 ** 23 - 1.0
+        assert abs(d[c, 0, 0] - want) <= 1e-15 * 4, (c, d[c, 0, 0], want)
+    for j in range(2):
+        for i in range(3):
+            p = 3 * j + i
+            for c in range(3):
+                want = float(cnn_ref.splitmix_uniform(seed, 3 * p + c))
+                assert abs(d[c, j, i] - want) <= 1e-14, (j, i, c)
+    # another seed moves every noisy entry
+    other = cnn_ref.normalise(*args, noise_amp=amp, noise_seed=12345)
+    assert (other[:3] != noisy[:3]).all() and np.array_equal(other[3:], clean[3:])
