@@ -166,6 +166,7 @@ def cpu_model() -> str:
 
 
 BATCH_PASS = 3  # steps per pass of the batched kernel
+BATCH_LAUNCH_PASSES = 16  # passes per persistent launch
 
 
 def batched_leg(steps, warmup, log):
@@ -189,7 +190,7 @@ def batched_leg(steps, warmup, log):
     rows = autotune.tune(cases, cache_path=cache, log=log, steps_per_pass=K, whole=True)
     with Sw2dBatch(cases, band_rows=rows) as b:
         b.set_time_blocking(K)
-        b.set_launch(steps_per_launch=16 * K, use_graph=True)
+        b.set_launch(steps_per_launch=BATCH_LAUNCH_PASSES * K, use_graph=True)
         b.step(warmup)
         b.step(steps)  # records the graph for this step count
         torch.cuda.synchronize()

@@ -121,16 +121,23 @@ def relu(z):
 
 
 # --------------------------------------------------------------------------- network
-def forward(x, params):
+def forward(x, params, store=None):
     """params: list of (W, b) for the 4 layers. Returns (output, cache of pre-activations
-    and layer inputs for backward)."""
+    and layer inputs for backward). ``store``, if given, is applied to every hidden
+    activation map after its ReLU: the precision in which an implementation keeps the maps
+    between layers (e.g. rounding to BF16); None keeps FP64."""
     acts = [_f64(x)]
     zs = []
     a = acts[0]
     for i, (W, b) in enumerate(params):
         z = conv3x3(a, W, b)
         zs.append(z)
-        a = relu(z) if i < len(params) - 1 else z
+        if i < len(params) - 1:
+            a = relu(z)
+            if store is not None:
+                a = _f64(store(a))
+        else:
+            a = z
         acts.append(a)
     return a, (acts, zs)
 

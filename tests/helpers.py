@@ -1,4 +1,4 @@
-"""Shared test helpers: relative L2, GPU runs through the C ABI, crop windows for big grids."""
+"""Shared test helpers: relative L2 and GPU runs through the C ABI."""
 import numpy as np
 
 
@@ -24,25 +24,3 @@ def gpu_run(case, nsteps=None, band_rows=None, k=None, steps_per_pass=1):
         red = sim.reduce(kk) if kk > 0 else None
         e, u, v = sim.state_numpy()
     return e, u, v, red
-
-
-def crop_window(case, j0, j1, i0, i1, nsteps):
-    """The sub-problem that determines cells [j0,j1) x [i0,i1) after nsteps: the stencil
-    reaches 2 cells per step, so a margin of 2*nsteps (+1 for the land ring) suffices.
-    Returns (sub-case arrays, offsets of the window inside the crop)."""
-    m = 2 * nsteps + 1
-    a0, a1 = max(0, j0 - m), min(case.ny, j1 + m)
-    b0, b1 = max(0, i0 - m), min(case.nx, i1 + m)
-    sl = (slice(a0, a1), slice(b0, b1))
-    mask = case.mask[sl].copy()
-    # a crop edge that is not the basin edge becomes land; it is > 2*nsteps cells away
-    if a0 > 0:
-        mask[0, :] = 0
-    if a1 < case.ny:
-        mask[-1, :] = 0
-    if b0 > 0:
-        mask[:, 0] = 0
-    if b1 < case.nx:
-        mask[:, -1] = 0
-    return dict(H=case.H[sl], mask=mask, eta=case.eta[sl], u=case.u[sl], v=case.v[sl],
-                nx=b1 - b0, ny=a1 - a0), (j0 - a0, i0 - b0)

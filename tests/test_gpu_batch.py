@@ -107,26 +107,44 @@ def test_batch_rejects_bad_instance():
     assert ei.value.code == _lib.SW2D_EINVAL
 
 
-def test_full_ensemble_1000_steps_sampled():
-    """The 256-member ensemble (sides 128..1024) for 1000 steps as the bench runs it;
-    sampled members against single-grid runs (bitwise) and the oracle."""
-    sizes = inputs.ensemble_sizes()
-    cases = inputs.ensemble(sizes=sizes, steps=1000)
-    print(f"ensemble cells {sum(c.nx * c.ny for c in cases)}", flush=True)
-    with Sw2dBatch(cases) as b:
-        b.step(1000)
+def test_full_ensemble_as_benchmarked(tmp_path):
+    """The 256-member ensemble (sides 128..1024) exactly as the benchmark runs it: autotuned
+    band heights, the steps per pass and steps per launch of the benchmark, HIP graph replay,
+    999 steps. Sampled members (the smallest, the largest and two others) bitwise equal to
+    the same basins stepped alone; the smallest and the largest against the oracle; every
+    member's folds finite and its displaced volume conserved to 1e-5."""
+    import bench
+    from paper_1711_04471_amd import autotune
+    K, launch = bench.BATCH_PASS, bench.BATCH_LAUNCH_PASSES * bench.BATCH_PASS
+    steps = 999 // K * K
+    cases = inputs.ensemble(steps=steps)
+    print(f"ensemble cells {sum(c.nx * c.ny for c in cases)}, K={K}, {launch} steps per launch", flush=True)
+    rows = autotune.tune(cases, cache_path=str(tmp_path / "tune.json"), steps_per_pass=K, whole=True)
+    print(f"autotuned rows {sorted(set(rows))}", flush=True)
+    with Sw2dBatch(cases, band_rows=rows) as b:
+        b.set_time_blocking(K)
+        b.set_launch(steps_per_launch=launch, use_graph=True)
+        b.step(steps)
         red = b.reduce()
-        picks = [int(np.argmin([c.nx * c.ny for c in cases])), 7, 100, 255]
+        sizes = [c.nx * c.ny for c in cases]
+        picks = [int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 100]
         got = {k: b.state_numpy(k) for k in picks}
+    assert (red["step"] == steps).all()
+    assert np.isfinite(red["vol_total"]).all() and np.isfinite(red["max_abs_u"]).all()
+    for k, c in enumerate(cases):
+        v0 = sw2d_ref.reduce(c.nx, c.ny, c.dx, c.dy, c.H, c.mask, c.eta, c.u, c.v)
+        assert abs(red["vol_disp"][k] - v0[1]) <= 1e-5 * abs(v0[1]), (k, red["vol_disp"][k], v0[1])
     for k in picks:
-        e, u, v, _ = gpu_run(cases[k], nsteps=1000, k=1)
+        e, u, v, _ = gpu_run(cases[k], nsteps=steps, k=1)
         for x, y in zip(got[k], (e, u, v)):
             assert np.array_equal(x, y), k
-    k = picks[0]
-    oe, ou, ov, ored = sw2d_ref.run_case(cases[k], nsteps=1000, nthreads=8)
-    assert max(rel_l2(got[k][0], oe), rel_l2(got[k][1], ou), rel_l2(got[k][2], ov)) <= 1e-5
-    np.testing.assert_allclose(red["vol_disp"][k], ored[-1, 1], rtol=1e-5)
-    assert np.isfinite(red["vol_total"]).all()
+    for k in picks[:2]:
+        print(f"oracle member {k} {cases[k].nx}x{cases[k].ny}", flush=True)
+        oe, ou, ov, ored = sw2d_ref.run_case(cases[k], nsteps=steps, nthreads=8)
+        assert max(rel_l2(got[k][0], oe), rel_l2(got[k][1], ou), rel_l2(got[k][2], ov)) <= 1e-5, k
+        np.testing.assert_allclose(red["vol_disp"][k], ored[-1, 1], rtol=1e-5)
+        np.testing.assert_allclose(red["max_abs_u"][k], ored[-1, 2], rtol=1e-5)
+        np.testing.assert_allclose(red["max_abs_v"][k], ored[-1, 3], rtol=1e-5)
 
 
 def test_autotuner_parity_guard_and_cache(tmp_path):

@@ -379,3 +379,153 @@ def test_fused_network_equals_the_layer_by_layer_chain(rng, shape):
     torch.cuda.synchronize()
     assert torch.isfinite(ref).all()
     assert torch.equal(ref.view(torch.int32), out.view(torch.int32))
+
+
+# Images with more 8 x 32 output tiles than twice the workgroups the device can hold at once
+# (at most 8 four-wave workgroups per CU x 256 CUs = 2048): every workgroup of the persistent
+# conv grid walks two or more tiles, prefetching the next patch into registers while the
+# current one is multiplied - the path every 1024^2 layer takes in training and inference.
+MAX_RESIDENT = 2048
+BIG = [(1, 1024, 1024), (2, 520, 1000)]
+
+
+def _tiles(N, H, Wd):
+    return N * ((H + 7) // 8) * ((Wd + 31) // 32)
+
+
+@pytest.mark.parametrize("shape", BIG)
+def test_conv_multi_tile_walk_matches_oracle(rng, shape):
+    """First layer (16 padded inputs), a hidden layer (32 inputs, ReLU + BF16 store) and the
+    last layer (FP32 planes) on images of 2+ tiles per workgroup, against the oracle."""
+    N, H, Wd = shape
+    assert _tiles(N, H, Wd) >= 2 * MAX_RESIDENT
+    print(f"multi-tile conv {shape}", flush=True)
+    for cin, creal, cout, relu in ((16, 5, 32, True), (32, 32, 32, True), (32, 32, 3, False)):
+        x = rng.standard_normal((N, creal, H, Wd))
+        if cin == 32:
+            x = np.maximum(x, 0)
+        W = rng.standard_normal((cout, creal, 3, 3)) * (0.3 if cin == 16 else 0.1)
+        b = rng.standard_normal(cout) * 0.1
+        out, x64, Wq = _fwd(x, W, b, cin, relu)
+        got = out.float().cpu().numpy() if relu else out.cpu().numpy()
+        for n in range(N):
+            want = cnn_ref.conv3x3(x64[n], Wq, b.astype(np.float32))
+            if relu:
+                want = cnn_ref.relu(want)
+                g = np.transpose(got[n], (2, 0, 1))
+                err = rel_l2(g, want)
+                assert err <= 4e-3, (cin, n, err)  # BF16 store of the output
+            else:
+                err = rel_l2(got[n], want)
+                assert err <= 1e-5, (cin, n, err)
+            print(f"  cin {cin} cout {cout} image {n}: rel-L2 {err:.3g}", flush=True)
+
+
+@pytest.mark.parametrize("shape", BIG)
+def test_conv_dgrad_multi_tile_walk_matches_oracle(rng, shape):
+    N, H, Wd = shape
+    assert _tiles(N, H, Wd) >= 2 * MAX_RESIDENT
+    W = rng.standard_normal((32, 32, 3, 3)) * 0.1
+    dy = rng.standard_normal((N, 32, H, Wd))
+    act = np.maximum(rng.standard_normal((N, 32, H, Wd)), 0)
+    master = torch.from_numpy(wk_layout(W, 32).astype(np.float32)).to(DEV)
+    wk = torch.empty((9, 32, 32), dtype=torch.bfloat16, device=DEV)
+    wd = torch.empty((9, 32, 32), dtype=torch.bfloat16, device=DEV)
+    check(lib().sw2d_cast_weights(ptr(master), 32, ptr(wk), ptr(wd), stream()))
+    dyb, dy64 = bf16(to_nhwc(dy, 32))
+    ab, a64 = bf16(to_nhwc(act, 32))
+    dx = torch.empty((N, H, Wd, 32), dtype=torch.bfloat16, device=DEV)
+    check(lib().sw2d_conv3x3_dgrad(ptr(dyb), ptr(wd), ptr(ab), ptr(dx), N, H, Wd, stream()))
+    torch.cuda.synchronize()
+    Wq = np.transpose(wk.to(torch.float64).cpu().numpy().reshape(3, 3, 32, 32), (2, 3, 0, 1))
+    got = dx.float().cpu().numpy()
+    for n in range(N):
+        want = cnn_ref.conv3x3_dgrad(np.transpose(dy64[n], (2, 0, 1)), Wq) * (np.transpose(a64[n], (2, 0, 1)) > 0)
+        err = rel_l2(np.transpose(got[n], (2, 0, 1)), want)
+        print(f"dgrad {shape} image {n}: rel-L2 {err:.3g}", flush=True)
+        assert err <= 4e-3, err
+
+
+@pytest.mark.parametrize("cin", [32, 16])
+def test_conv_wgrad_training_minibatch_matches_oracle(rng, cin):
+    """The weight gradient at the training minibatch (4 images of 1024^2): 1024 chunks of
+    16 tiles, so each of the reduction's 8 slices adds 128 partials in order."""
+    N, H, Wd = 4, 1024, 1024
+    creal = 5 if cin == 16 else 32
+    print(f"wgrad {N}x{H}x{Wd} cin {cin}", flush=True)
+    x = rng.standard_normal((N, creal, H, Wd)).astype(np.float32)
+    if cin == 32:
+        x = np.maximum(x, 0)
+    dy = (rng.standard_normal((N, 32, H, Wd)) * 0.1).astype(np.float32)
+    xb, x64 = bf16(to_nhwc(x, cin))
+    dyb, dy64 = bf16(to_nhwc(dy, 32))
+    del x, dy
+    need = lib().sw2d_wgrad_workspace_bytes(cin, N, H, Wd)
+    assert need >= 1024 * 9 * 32 * cin * 4
+    work = torch.empty(need, dtype=torch.uint8, device=DEV)
+    dW = torch.empty((9, 32, cin), dtype=torch.float32, device=DEV)
+    db = torch.empty(32, dtype=torch.float32, device=DEV)
+    check(lib().sw2d_conv3x3_wgrad(ptr(xb), cin, ptr(dyb), N, H, Wd, ptr(dW), ptr(db), ptr(work), need, stream()))
+    torch.cuda.synchronize()
+    want_W = np.zeros((32, cin, 3, 3))
+    want_b = np.zeros(32)
+    for n in range(N):
+        gw, gb = cnn_ref.conv3x3_wgrad(np.transpose(x64[n], (2, 0, 1)), np.transpose(dy64[n], (2, 0, 1)))
+        want_W += gw
+        want_b += gb
+    got_W = np.transpose(dW.cpu().numpy().reshape(3, 3, 32, cin), (2, 3, 0, 1))
+    err_w, err_b = rel_l2(got_W, want_W), rel_l2(db.cpu().numpy(), want_b)
+    print(f"  rel-L2 dW {err_w:.3g} db {err_b:.3g}", flush=True)
+    assert err_w <= 1e-4 and err_b <= 1e-4, (err_w, err_b)
+    if cin == 16:  # padded input channels carry exactly zero gradient
+        assert not got_W[:, creal:].any()
+
+
+def _bf16_round(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("shape", [(1024, 1024), (130, 257), (37, 45)])
+def test_fused_network_matches_oracle_forward(rng, shape):
+    """The one-kernel network (sw2d_cnn_forward, the kernel the rollout runs) against the
+    oracle's forward pass from the raw coarse state, with the oracle storing the input and
+    the hidden maps in BF16 where the kernel does. The residual comes from maps whose FP32
+    and FP64 values round to neighbouring BF16 numbers (one BF16 unit, 2^-8 relative, on a
+    small fraction of the entries), bounded here by 1e-3 relative L2."""
+    H, W = shape
+    print(f"fused forward vs oracle {H}x{W}", flush=True)
+    eta = (rng.standard_normal((H, W)) * 0.3).astype(np.float32)
+    u = (rng.standard_normal((H, W)) * 0.1).astype(np.float32)
+    v = (rng.standard_normal((H, W)) * 0.1).astype(np.float32)
+    Hd = rng.uniform(5, 50, (H, W)).astype(np.float32)
+    mask = (rng.uniform(size=(H, W)) < 0.85).astype(np.uint8)
+    mean = np.array([0.01, 0.0, 0.0, 25.0, 0.85], dtype=np.float32)
+    std = np.array([0.3, 0.1, 0.1, 12.0, 0.36], dtype=np.float32)
+    mp = mean.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    sp = std.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    g = [torch.as_tensor(a).to(DEV) for a in (eta, u, v, Hd, mask)]
+    wks, biases, params = [], [], []
+    for cin, real_in, real_out, scale in ((16, 5, 32, 0.3), (32, 32, 32, 0.1), (32, 32, 32, 0.1), (32, 32, 3, 0.05)):
+        Wm = torch.from_numpy(wk_layout(rng.standard_normal((real_out, real_in, 3, 3)) * scale, cin)
+                              .astype(np.float32)).to(DEV)
+        wk = torch.empty((9, 32, cin), dtype=torch.bfloat16, device=DEV)
+        check(lib().sw2d_cast_weights(ptr(Wm), cin, ptr(wk), None, stream()))
+        b = torch.zeros(32, dtype=torch.float32, device=DEV)
+        b[:real_out] = torch.from_numpy((rng.standard_normal(real_out) * 0.1).astype(np.float32))
+        wks.append(wk)
+        biases.append(b)
+        torch.cuda.synchronize()
+        wq = np.transpose(wk.to(torch.float64).cpu().numpy().reshape(3, 3, 32, cin), (2, 3, 0, 1))
+        params.append((wq[:real_out, :real_in], b.cpu().numpy()[:real_out].astype(np.float64)))
+    out = torch.full((3, H, W), float("nan"), dtype=torch.float32, device=DEV)
+    wk_arr = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in wks])
+    b_arr = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in biases])
+    check(lib().sw2d_cnn_forward(*map(ptr, g), W, H, mp, sp, wk_arr, b_arr, ptr(out), stream()))
+    torch.cuda.synchronize()
+    x = _bf16_round(cnn_ref.normalise(eta, u, v, Hd, mask, mean, std))
+    want, _ = cnn_ref.forward(x, params, store=_bf16_round)
+    got = out.cpu().numpy()
+    assert np.isfinite(got).all()
+    err = rel_l2(got, want)
+    print(f"  rel-L2 {err:.3g}", flush=True)
+    assert err <= 1e-3, err

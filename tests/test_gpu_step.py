@@ -4,7 +4,6 @@ Bar: eta, u, v within 1e-5 relative L2 of the oracle after the stated steps; lan
 inactive faces and the nonzero pattern of a one-step impulse exactly equal; lake at
 rest bitwise; bitwise determinism and bitwise independence of the band height.
 """
-import math
 import os
 
 import numpy as np
@@ -12,7 +11,7 @@ import pytest
 
 from oracle import sw2d_ref
 from paper_1711_04471_amd import inputs
-from tests.helpers import crop_window, gpu_run, rel_l2
+from tests.helpers import gpu_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -88,34 +87,25 @@ def test_basin_2048_1000_steps():
 BENCH_PASS = (4, 104)
 
 
-def test_basin_8192_500_steps_sampled_windows():
-    """The full 8192^2 headline run in the benchmark's launch configuration, checked on
-    windows the oracle computes exactly from their dependency cone, plus volume conservation
-    over the whole basin; the state equals single steps bit for bit."""
+def test_basin_8192_500_steps_full_field():
+    """The 8192^2 headline run (500 steps) in the benchmark's launch configuration against
+    the oracle on the whole basin: eta, u, v within 1e-5 relative L2, land and inactive faces
+    exactly zero, all four folds of every one of the 500 steps within 1e-5; the state also
+    equals single steps bit for bit."""
     c = inputs.basin_8192()
     _say(f"case {c.name} {c.nx}x{c.ny} steps {c.steps}, {BENCH_PASS[0]} steps per pass, {BENCH_PASS[1]} rows")
     e, u, v, red = gpu_run(c, steps_per_pass=BENCH_PASS[0], band_rows=BENCH_PASS[1])
     e1, u1, v1, red1 = gpu_run(c)
     assert np.array_equal(e, e1) and np.array_equal(u, u1) and np.array_equal(v, v1)
+    del e1, u1, v1
     np.testing.assert_allclose(red["vol_disp"], red1["vol_disp"], rtol=1e-12, atol=1e-9 * c.dx * c.dy)
-    v0 = sw2d_ref.reduce(c.nx, c.ny, c.dx, c.dy, c.H, c.mask, c.eta, c.u, c.v)
-    assert abs(red["vol_disp"][-1] - v0[1]) <= 1e-5 * abs(v0[1])
-    assert abs(red["vol_total"][-1] - v0[0]) <= 1e-5 * abs(v0[1])
-    w = 48
-    for (j0, i0) in ((8192 - w, 8192 - w), (4100, 3000)):
-        sub, (oj, oi) = crop_window(c, j0, j0 + w, i0, i0 + w, c.steps)
-        _say(f"window ({j0},{i0}) crop {sub['nx']}x{sub['ny']}")
-        oe, ou, ov, _ = sw2d_ref.run(sub["nx"], sub["ny"], c.dx, c.dy, c.g, c.dt, c.eps, sub["H"],
-                                     sub["mask"], sub["eta"], sub["u"], sub["v"], c.steps,
-                                     nthreads=NTHREADS, reductions=False)
-        win = (slice(oj, oj + w), slice(oi, oi + w))
-        gw = (slice(j0, j0 + w), slice(i0, i0 + w))
-        for name, g, o in (("eta", e, oe), ("u", u, ou), ("v", v, ov)):
-            ref = o[win]
-            if np.linalg.norm(ref) > 0:
-                assert rel_l2(g[gw], ref) <= TOL, (name, j0, i0, rel_l2(g[gw], ref))
-            else:
-                assert np.abs(g[gw]).max() <= 1e-6
+    assert np.array_equal(red["step"], np.arange(1, c.steps + 1))
+    _say(f"oracle {c.steps} steps on {NTHREADS} threads")
+    oe, ou, ov, ored = sw2d_ref.run_case(c, nthreads=NTHREADS)
+    errs = _check_state(c, e, u, v, oe, ou, ov)
+    _say(f"rel-L2 eta/u/v {errs}")
+    for col, k in (("vol_total", 0), ("vol_disp", 1), ("max_abs_u", 2), ("max_abs_v", 3)):
+        np.testing.assert_allclose(red[col], ored[:, k], rtol=TOL, atol=0, err_msg=col)
 
 
 def test_impulse_pattern_and_face_activity_are_exact():
