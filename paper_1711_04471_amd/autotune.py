@@ -4,8 +4,9 @@ Instances are grouped by width into size classes; for each class the candidate b
 heights are timed on that class's instances alone (a batch of them, HIP-event timed
 steps after a warm-up). A candidate is only eligible if the state it produces is
 bitwise equal to every other candidate's (the parity guard: the band height may change
-speed, never results). Results are cached in a JSON file keyed by GPU architecture,
-class bounds and candidate set.
+speed, never results). Results are cached in a JSON file keyed by GPU architecture, steps
+per pass, class bounds, candidate set and a digest of the member shapes, so a different
+ensemble never reuses another's choice.
 """
 
 from __future__ import annotations
@@ -27,6 +28,11 @@ def size_class(nx: int):
         if lo <= nx < hi:
             return (lo, hi)
     return None
+
+
+def _shapes(cases) -> str:
+    """Digest of the members' grid sizes, in member order (part of every cache key)."""
+    return hashlib.sha1(",".join(f"{int(c.nx)}x{int(c.ny)}" for c in cases).encode()).hexdigest()[:12]
 
 
 def _digest(batch) -> str:
@@ -65,9 +71,9 @@ def tune(cases, candidates=None, cache_path=None, steps=24, warmup=6, device="cu
     for cls, idx in by_class.items():
         if cls is None:
             continue
-        key = f"{arch}|K{steps_per_pass}|{cls[0]}-{cls[1]}|{','.join(map(str, candidates))}"
+        sub = [cases[i] for i in idx]
+        key = f"{arch}|K{steps_per_pass}|{cls[0]}-{cls[1]}|{','.join(map(str, candidates))}|{_shapes(sub)}"
         if key not in cache:
-            sub = [cases[i] for i in idx]
             timing, digests = {}, {}
             for cand in candidates:
                 with Sw2dBatch(sub, band_rows=[cand] * len(sub), device=dev) as b:
@@ -88,7 +94,7 @@ def tune(cases, candidates=None, cache_path=None, steps=24, warmup=6, device="cu
         # the classes share one grid, so the best heights class by class need not be the best
         # together: time the tuned assignment against each uniform height on the whole batch
         key = f"{arch}|K{steps_per_pass}|whole|{len(cases)}|{','.join(map(str, candidates))}|" \
-              f"{hashlib.sha1(json.dumps(rows).encode()).hexdigest()[:12]}"
+              f"{hashlib.sha1(json.dumps(rows).encode()).hexdigest()[:12]}|{_shapes(cases)}"
         if key not in cache:
             options = {"tuned": rows}
             options.update({str(c): [c] * len(cases) for c in candidates})

@@ -775,7 +775,8 @@ __global__ __launch_bounds__(256) void sqdiff_kernel(const float* __restrict__ a
                                                      double* __restrict__ partial) {
     __shared__ double lds[256];
     double s = 0.0;
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    // 64-bit index: n may come close to 2^31, and the stride would overflow an int
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         if (mask[i]) {
             const double d = (double)a[i] - (double)b[i];
             s += d * d;

@@ -21,13 +21,14 @@ from __future__ import annotations
 import ctypes
 import math
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 import torch
 
 from . import _lib, inputs
 from ._lib import check
+from .judge import RolloutResult, judged_rollout  # noqa: F401  (RolloutResult: rollout's type)
 from .sw2d import Sw2d
 
 CIN = (16, 32, 32, 32)  # padded input channels per layer (5 real channels in the first)
@@ -427,14 +428,6 @@ class Trainer:
         return history
 
 
-@dataclass
-class RolloutResult:
-    rmse: list = field(default_factory=list)  # eta RMSE at each judge, before any reset
-    fallbacks: int = 0
-    surrogate_s: float = 0.0   # coarse steps + network + resets
-    judge_s: float = 0.0       # the fine audit runs
-
-
 def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1e-3, device="cuda",
             fine: Sw2d | None = None, damping=0.5, correct_every=1):
     """Advance the surrogate n_coarse coarse steps from the restricted initial state of
@@ -453,44 +446,37 @@ def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1
         fine = Sw2d.from_case(case, device=dev)
     co = Coarse(fine, case)
     s = torch.cuda.current_stream(dev).cuda_stream
-    res = RolloutResult()
     ref = [torch.empty_like(co.eta) for _ in range(3)] + [torch.empty_like(co.H), torch.empty_like(co.mask)]
     if net is not None:
         mean_a, mp = _fptr(net.stats.in_mean)
         std_a, sp = _fptr(net.stats.in_std)
         tstd_a, tp = _fptr(net.stats.t_std * damping)
-    for seg in range(n_coarse // judge_every):
-        torch.cuda.synchronize(dev)
-        t0 = time.perf_counter()
+
+    def advance(n):
         if net is None:
-            co.sim.step(judge_every)
+            co.sim.step(n)
         elif correct_every == 1:
             # the network sees the state before each coarse step, as in training; one kernel
             # runs all four layers and its output corrects the stepped state
-            net.advance(co.sim, judge_every, co.H, co.mask, mp, sp, tp)
+            net.advance(co.sim, n, co.H, co.mask, mp, sp, tp)
         else:
-            for _ in range(judge_every // correct_every):
+            for _ in range(n // correct_every):
                 e, u, v = co.sim.state()
                 out = net.forward_fused(e, u, v, co.H, co.mask, co.sim.ny, co.sim.nx, mp, sp)
                 co.sim.step(correct_every)
                 e, u, v = co.sim.state()
                 check(lib.sw2d_apply_correction(_p(e), _p(u), _p(v), _p(out), _p(co.mask), co.sim.nx, co.sim.ny,
                                                 tp, s), "sw2d_apply_correction")
-        torch.cuda.synchronize(dev)
-        t1 = time.perf_counter()
-        fine.step(4 * judge_every)
+
+    def fine_advance(n):
+        fine.step(n)
         co.restrict(fine, out=ref)
-        torch.cuda.synchronize(dev)
-        t2 = time.perf_counter()
-        err = co.rmse_eta(ref[0])
-        res.rmse.append(err)
-        if not err <= threshold:  # a non-finite error falls back too
-            co.sim.set_state(ref[0], ref[1], ref[2], step=co.sim.steps_done)
-            res.fallbacks += 1
-        torch.cuda.synchronize(dev)
-        t3 = time.perf_counter()
-        res.surrogate_s += (t1 - t0) + (t3 - t2)
-        res.judge_s += t2 - t1
+
+    def reset():
+        co.sim.set_state(ref[0], ref[1], ref[2], step=co.sim.steps_done)
+
+    res = judged_rollout(advance, fine_advance, lambda: co.rmse_eta(ref[0]), reset, n_coarse, judge_every,
+                         threshold, sync=lambda: torch.cuda.synchronize(dev))
     co.sim.close()
     if own_fine:
         fine.close()

@@ -28,3 +28,16 @@ def test_roofline_constants():
     assert bench.VALU_PEAK_TFLOPS == pytest.approx(78.6432)
     # eta, u, v, H read and eta, u, v written, 4 bytes each
     assert bench.BYTES_PER_CELL_STEP == 4 * (4 + 3)
+    # MI355X's published FP32 vector peak (packed two-wide FMAs counted)
+    assert bench.VALU_PEAK_PUBLISHED_TFLOPS == 157.3
+    assert bench.REPS >= 5
+
+
+@pytest.mark.parametrize("m", ["0", "3", "4", "7"])
+def test_surrogate_interval_must_divide_the_judge_interval(m):
+    """Refused before any GPU work: the rollout needs m to divide the 50-step judge interval."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--surrogate-every", m, "--only-surrogate"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "divisor of the judge interval" in r.stderr
+    assert r.stdout == ""
