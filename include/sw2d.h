@@ -26,7 +26,8 @@
  *
  * Ownership: the caller owns every device buffer (state, depth, mask, workspace)
  * and the HIP stream; they must outlive the handle. The library owns only its
- * host-side handle and never allocates device memory.
+ * host-side handle and never allocates device memory; the one fixed device array it
+ * holds is the staging buffer of sw2d_surrogate_advance_noalloc.
  *
  * Errors: every call returns an int status (SW2D_OK or a negative code below);
  * nothing throws or aborts across the ABI. Work is enqueued asynchronously on the
@@ -49,7 +50,8 @@ enum {
     SW2D_EHIP = -2,      /* a HIP runtime call failed; see sw2d_strerror / sw2d_last_hip_error */
     SW2D_EUNSTABLE = -3, /* a fold came back non-finite: the run has blown up */
     SW2D_ESTATE = -4,    /* handle misuse (NULL handle, bad k, ...) */
-    SW2D_ENOSPC = -5     /* workspace smaller than sw2d_workspace_bytes() */
+    SW2D_ENOSPC = -5     /* workspace smaller than sw2d_workspace_bytes(), or a grid larger
+                            than a fixed library array holds */
 };
 
 /* Model variants (flags of sw2d_params; the paper's model has neither - they are the
@@ -370,6 +372,23 @@ int sw2d_cnn_forward(const float *eta, const float *u, const float *v, const flo
 int sw2d_surrogate_advance(sw2d_t coarse, int32_t nsteps, const float *H, const uint8_t *mask, const float *mean,
                            const float *std_, const uint16_t *const *wk, const float *const *bias,
                            const float *t_std, float *delta);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sw2d_surrogate_advance without the delta
+ * argument. The network output is staged in a fixed library array of 3 *
+ * SW2D_NOALLOC_MAX_CELLS floats per device (24 MiB, taken when the library's code is loaded
+ * on that device and held until the process ends), so the coarse grid may have at most
+ * SW2D_NOALLOC_MAX_CELLS cells: a larger one returns SW2D_ENOSPC before anything is enqueued.
+ * Every call on one device shares that array and the network overwrites every entry it later
+ * reads, so no state carries over between calls; calls that overlap on one device (two
+ * streams, two threads) race on it and must be serialised by the caller. Allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine (the first call on a device looks up
+ * the array's device address once). Other arguments and errors as sw2d_surrogate_advance;
+ * the resulting state is bitwise the same. */
+#define SW2D_NOALLOC_MAX_CELLS 2097152
+int sw2d_surrogate_advance_noalloc(sw2d_t coarse, int32_t nsteps, const float *H, const uint8_t *mask,
+                                   const float *mean, const float *std_, const uint16_t *const *wk,
+                                   const float *const *bias, const float *t_std);
 
 /* The last layer (cin 32 -> channels 0..2 plus bias) of one image with its output added to
  * the state as sw2d_apply_correction does (t_std: host array of 3 scales), without the

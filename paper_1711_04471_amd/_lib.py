@@ -95,6 +95,9 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _vp, _vp]),
     "sw2d_surrogate_advance": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _fp, _fp, ctypes.POINTER(ctypes.c_void_p),
                                               ctypes.POINTER(ctypes.c_void_p), _fp, _vp]),
+    "sw2d_surrogate_advance_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _fp, _fp,
+                                                      ctypes.POINTER(ctypes.c_void_p),
+                                                      ctypes.POINTER(ctypes.c_void_p), _fp]),
     "sw2d_conv3x3_correct": (ctypes.c_int, [_vp, _vp, _vp, _fp, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                             ctypes.c_int32, _vp]),
     "sw2d_conv3x3_fwd": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp] +

@@ -411,7 +411,7 @@ const char* sw2d_strerror(int code) {
         case SW2D_EHIP: return "HIP runtime error";
         case SW2D_EUNSTABLE: return "non-finite folds: the run is unstable";
         case SW2D_ESTATE: return "invalid handle use";
-        case SW2D_ENOSPC: return "workspace too small";
+        case SW2D_ENOSPC: return "workspace too small (or a grid larger than a fixed library array holds)";
         default: return "unknown status";
     }
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "sw2d_internal.h"
 #include "sw2d_handle.h"
@@ -29,6 +30,58 @@ bool aligned16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0;
 
 constexpr int kMseBlocks = 1024;
 constexpr int kRmseBlocks = 1024;
+
+// Staging of the network output for sw2d_surrogate_advance_noalloc: three FP32 planes of a
+// coarse grid of at most SW2D_NOALLOC_MAX_CELLS cells. Each device holds its own copy at its
+// own address; host code uses only the address hipGetSymbolAddress returns for a device,
+// never the array's name (which on the host is a stand-in, not a device address).
+static __device__ __align__(256) float scratch[3 * (size_t)SW2D_NOALLOC_MAX_CELLS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that owns stream s, looked up once per device
+// with that device current.
+int scratch_for_stream(hipStream_t s, float** out) {
+    int dev = -1;
+    hipError_t e = hipStreamGetDevice(s, &dev);
+    if (e != hipSuccess) return fail(e, "sw2d_surrogate_advance_noalloc: hipStreamGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return SW2D_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = -1;
+        e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void* ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return fail(e, "sw2d_surrogate_advance_noalloc: hipGetSymbolAddress");
+        if (!ptr) return SW2D_EHIP;
+        g_scratch_dev[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return SW2D_OK;
+}
+
+// n corrected coarse steps with the network output staged in `delta` (3 planes of the grid).
+int advance_corrected(sw2d_t coarse, hipStream_t s, int nx, int ny, int32_t nsteps, const float* H,
+                      const uint8_t* mask, const float* mean, const float* std_, const uint16_t* const* wk,
+                      const float* const* bias, const float* t_std, float* delta) {
+    for (int32_t n = 0; n < nsteps; ++n) {
+        float *e, *u, *v;
+        int rc = sw2d_state(coarse, &e, &u, &v);
+        if (rc == SW2D_OK) rc = sw2d_cnn_forward(e, u, v, H, mask, nx, ny, mean, std_, wk, bias, delta, s);
+        if (rc == SW2D_OK) rc = sw2d_step(coarse, 1);
+        if (rc == SW2D_OK) rc = sw2d_state(coarse, &e, &u, &v);
+        if (rc == SW2D_OK) rc = fail(launch_correct(e, u, v, delta, mask, ny, nx, t_std, s), "sw2d_surrogate_advance");
+        if (rc != SW2D_OK) return rc;
+    }
+    return SW2D_OK;
+}
 
 }  // namespace
 
@@ -126,16 +179,23 @@ int sw2d_surrogate_advance(sw2d_t coarse, int32_t nsteps, const float* H, const 
     if (!H || !mask || !mean || !std_ || !wk || !bias || !t_std || !delta) return SW2D_EINVAL;
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(t_std[c])) return SW2D_EINVAL;
-    for (int32_t n = 0; n < nsteps; ++n) {
-        float *e, *u, *v;
-        int rc = sw2d_state(coarse, &e, &u, &v);
-        if (rc == SW2D_OK) rc = sw2d_cnn_forward(e, u, v, H, mask, nx, ny, mean, std_, wk, bias, delta, s);
-        if (rc == SW2D_OK) rc = sw2d_step(coarse, 1);
-        if (rc == SW2D_OK) rc = sw2d_state(coarse, &e, &u, &v);
-        if (rc == SW2D_OK) rc = fail(launch_correct(e, u, v, delta, mask, ny, nx, t_std, s), "sw2d_surrogate_advance");
-        if (rc != SW2D_OK) return rc;
-    }
-    return SW2D_OK;
+    return advance_corrected(coarse, s, nx, ny, nsteps, H, mask, mean, std_, wk, bias, t_std, delta);
+}
+
+int sw2d_surrogate_advance_noalloc(sw2d_t coarse, int32_t nsteps, const float* H, const uint8_t* mask,
+                                   const float* mean, const float* std_, const uint16_t* const* wk,
+                                   const float* const* bias, const float* t_std) {
+    hipStream_t s = nullptr;
+    int nx = 0, ny = 0;
+    if (!sw2d::detail::handle_info(coarse, &s, &nx, &ny) || nsteps < 0) return SW2D_ESTATE;
+    if (!H || !mask || !mean || !std_ || !wk || !bias || !t_std) return SW2D_EINVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(t_std[c])) return SW2D_EINVAL;
+    if ((int64_t)nx * ny > SW2D_NOALLOC_MAX_CELLS) return SW2D_ENOSPC;
+    float* delta = nullptr;
+    const int rc = scratch_for_stream(s, &delta);
+    if (rc != SW2D_OK) return rc;
+    return advance_corrected(coarse, s, nx, ny, nsteps, H, mask, mean, std_, wk, bias, t_std, delta);
 }
 
 int sw2d_conv3x3_correct(const uint16_t* in, const uint16_t* wk, const float* bias, const float* t_std,

@@ -157,6 +157,14 @@ class ConvNet:
         check(self.lib.sw2d_surrogate_advance(sim._handle(), int(nsteps), _p(H), _p(mask), mean_ptr, std_ptr, wk, bias,
                                               tstd_ptr, _p(out)), "sw2d_surrogate_advance")
 
+    def advance_noalloc(self, sim, nsteps, H, mask, mean_ptr, std_ptr, tstd_ptr):
+        """``advance`` with the network output staged in the library's fixed device array
+        instead of a buffer of this object (for callers that cannot allocate)."""
+        wk = (ctypes.c_void_p * 4)(*[t.data_ptr() for t in self.wk])
+        bias = (ctypes.c_void_p * 4)(*[self.weight(layer)[1].data_ptr() for layer in range(4)])
+        check(self.lib.sw2d_surrogate_advance_noalloc(sim._handle(), int(nsteps), _p(H), _p(mask), mean_ptr, std_ptr,
+                                                      wk, bias, tstd_ptr), "sw2d_surrogate_advance_noalloc")
+
     def correct(self, hidden, eta, u, v, mask, h, w, tstd_ptr):
         """Layer 4 with its output added to the state as the correction (fused)."""
         check(self.lib.sw2d_conv3x3_correct(_p(hidden), _p(self.wk[3]), _p(self.weight(3)[1]), tstd_ptr, _p(mask),

@@ -130,3 +130,4 @@ def test_surrogate_entry_points_check_arguments_on_the_host(lib):
     assert L.sw2d_cnn_forward(*args, 0, 8, mean, std, wk, bias, dummy, None) == _lib.SW2D_EINVAL
     t_std = (ctypes.c_float * 3)(1, 1, 1)
     assert L.sw2d_surrogate_advance(None, 1, dummy, dummy, mean, std, wk, bias, t_std, dummy) == _lib.SW2D_ESTATE
+    assert L.sw2d_surrogate_advance_noalloc(None, 1, dummy, dummy, mean, std, wk, bias, t_std) == _lib.SW2D_ESTATE
