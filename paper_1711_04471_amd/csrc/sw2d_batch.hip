@@ -34,7 +34,6 @@
 #include <vector>
 
 #include "sw2d_internal.h"
-#include "sw2d_pair.h"
 #include "sw2d_tile.h"
 
 namespace sw2d {
@@ -80,22 +79,11 @@ struct BatchControl {
 
 constexpr int kBatchThreads = kGroupThreads;
 constexpr int kMaxBatchK = 3;  // steps per pass of the batched kernel: 1..3
-// Two columns per lane for K >= 2 (as the single-grid K-step kernel) measured slower on the
-// ensemble (327,100 against 338,600 Mcell-steps/s at K = 3, 64-row bands): the members are
-// small, odd widths need 4-byte accesses, and the persistent grid drops from 4 to 3 resident
-// workgroups per CU. Off by default.
-#ifndef SW2D_BATCH_PAIR
-#define SW2D_BATCH_PAIR 0
-#endif
-#if SW2D_BATCH_PAIR
-#define SW2D_BATCH_WAVES __attribute__((amdgpu_waves_per_eu(3)))
-#else
-#define SW2D_BATCH_WAVES
-#endif
-// Owned columns of a strip for K steps per pass.
-constexpr int batch_strip_out(int K) {
-    return K == 1 ? kStripOut : (SW2D_BATCH_PAIR ? 2 * kWave : kWave) - 4 * K;
-}
+// Owned columns of a strip for K steps per pass: one column per lane. (Two columns per lane,
+// as the single-grid K-step kernel, measured slower on the ensemble: the members are small,
+// odd widths need 4-byte accesses, and the persistent grid drops from 4 to 3 resident
+// workgroups per CU.)
+constexpr int batch_strip_out(int K) { return K == 1 ? kStripOut : kWave - 4 * K; }
 constexpr int kBatchRing = 64;  // steps of per-instance folds kept
 
 struct BatchArgs {
@@ -231,18 +219,15 @@ __device__ __forceinline__ float uniform_f(float x) {
 
 // K steps per pass over each member (temporal blocking as in the single-grid K-step
 // kernel: bands read a 2K-row halo, strips lose 2K columns on each side); the grid meets once
-// per pass. For K >= 2 a lane holds two adjacent columns (SW2D_BATCH_PAIR: strips of 128 - 4K
-// owned columns, 4-byte row accesses since members may have odd widths), otherwise one.
+// per pass.
 template <int K>
-__global__ __launch_bounds__(kBatchThreads) SW2D_BATCH_WAVES void sw2d_batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) {
     __shared__ BatchTile s_tiles[kLdsTiles];
     __shared__ int s_ids[kLdsTiles];
     __shared__ double s_disp[kWavesPerGroup];
     __shared__ float s_mu[kWavesPerGroup], s_mv[kWavesPerGroup];
-    constexpr bool kPair = SW2D_BATCH_PAIR && K >= 2;
     constexpr int kOut = batch_strip_out(K);
     constexpr int kEdge = (K == 1) ? kHalo : 2 * K;  // unowned columns on each side of a strip
-    constexpr int kEdgeLanes = kPair ? K : kEdge;
     const int nwg = gridDim.x;
     const int lwg = logical_block(blockIdx.x, nwg);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -281,10 +266,9 @@ __global__ __launch_bounds__(kBatchThreads) SW2D_BATCH_WAVES void sw2d_batch_ker
             const int nx = uniform(t.nx), ny = uniform(t.ny);
             const int group2 = uniform(t.group2);
             const int strip = (group2 >> 1) * kWavesPerGroup + wave;
-            // this lane's (first) column
-            const int c = strip * kOut - kEdge + (kPair ? 2 * lane : lane);
+            const int c = strip * kOut - kEdge + lane;  // this lane's column
             const bool col_in = c >= 0 && c < nx;
-            const bool out_lane = col_in && lane >= kEdgeLanes && lane < kWave - kEdgeLanes;
+            const bool out_lane = col_in && lane >= kEdge && lane < kWave - kEdge;
             LaneFolds F[K];
             if (strip < uniform(t.strips)) {
                 StepCoef kc;
@@ -314,13 +298,6 @@ __global__ __launch_bounds__(kBatchThreads) SW2D_BATCH_WAVES void sw2d_batch_ker
                     F[0].disp = f_disp;
                     F[0].mu_bits = __float_as_uint(f_mu);
                     F[0].mv_bits = __float_as_uint(f_mv);
-                } else if constexpr (kPair) {
-                    if (group2 & 1)
-                        marchK_pair<K, false, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0,
-                                                     j1, kc, F);
-                    else
-                        marchK_pair<K, true, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0,
-                                                    j1, kc, F);
                 } else {
                     if (group2 & 1)
                         marchK<K, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, F);

@@ -12,16 +12,10 @@ constexpr int kWave = 64;                            // CDNA wavefront width
 constexpr int kHalo = 2;                             // stencil radius of the fused step
 constexpr int kStripOut = kWave - 2 * kHalo;         // output columns per wave strip (60)
 constexpr int kMaxStepsPerPass = 4;                 // temporal blocking depth (K steps per pass)
-// K >= 2 steps per pass: two adjacent columns per lane (SW2D_PAIR_COLUMNS, owned columns of
-// a strip 120, 116, 112) or one (60, 56, 52, 48).
-#ifndef SW2D_PAIR_COLUMNS
-#define SW2D_PAIR_COLUMNS 1
-#endif
-constexpr int strip_out_for(int K) { return (SW2D_PAIR_COLUMNS && K >= 2 ? 2 * kWave : kWave) - 4 * K; }
-#ifndef SW2D_WAVES_PER_GROUP
-#define SW2D_WAVES_PER_GROUP 4
-#endif
-constexpr int kWavesPerGroup = SW2D_WAVES_PER_GROUP;  // strips per workgroup
+// Owned columns of a strip at K steps per pass: the plain model at K >= 2 takes two adjacent
+// columns per lane (120, 116, 112), one step per pass one column (60).
+constexpr int strip_out_for(int K) { return (K >= 2 ? 2 * kWave : kWave) - 4 * K; }
+constexpr int kWavesPerGroup = 4;                    // strips per workgroup
 constexpr int kGroupThreads = kWave * kWavesPerGroup;
 constexpr int kGroupCols = kStripOut * kWavesPerGroup;  // 240 output columns per workgroup
 constexpr int kFoldThreads = 256;

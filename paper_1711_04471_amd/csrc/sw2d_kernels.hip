@@ -23,15 +23,6 @@
 // (LDS, fixed order) -> one partial per workgroup and step; sw2d_fold_kernel later adds
 // the partials of each step in a fixed order, so the folds are bitwise reproducible.
 // The static part of the total volume, sum_wet H, is folded once per handle.
-//
-// Compile-time options (defaults are the tuned choice):
-//   SW2D_PREFETCH  rows loaded ahead of the one being processed (1 or 2)
-//   SW2D_DPP       1: neighbour exchange with wave-wide DPP row shifts, 0: ds_bpermute
-//   SW2D_NT_STORE  1: non-temporal stores of the new state
-//   SW2D_XCD_MAP   1: XCD-contiguous workgroup -> tile mapping
-//   SW2D_ZIGZAG    1: odd bands march south (band-boundary rows are re-read from L2)
-//   SW2D_BAND_BLOCK vertically adjacent bands dispatched back to back (1 = plain
-//                  row-major tile order)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,17 +32,22 @@
 
 namespace sw2d {
 
-__device__ __forceinline__ int tile_of_block(int b, int n) {
-#if SW2D_XCD_MAP
-    // Workgroup b is dispatched to XCD b % 8; give each XCD a contiguous range of
-    // logical tiles so halo rows and columns shared by neighbours hit the same L2.
-    const int q = n / kXcds, r = n % kXcds;
-    const int x = b % kXcds, k = b / kXcds;
-    return x * q + min(x, r) + k;
-#else
-    (void)n;
-    return b;
-#endif
+// Band and strip group of workgroup b. Workgroup b is dispatched to XCD b % 8; each XCD
+// gets a contiguous range of logical tiles so that halo rows and columns shared by
+// neighbours hit the same L2. Logical tiles run through blocks of two vertically adjacent
+// bands, strip group by strip group, so the two bands of a block are dispatched together.
+constexpr int kBandBlock = 2;
+
+__device__ __forceinline__ int2 band_and_group(int b, int nblocks, int groups_x, int bands) {
+    const int q = nblocks / kXcds, r = nblocks % kXcds;
+    const int x = b % kXcds, kq = b / kXcds;
+    const int tile = x * q + min(x, r) + kq;
+    const int per_block = groups_x * kBandBlock;
+    const int blk = tile / per_block;
+    const int rem = tile - blk * per_block;
+    const int nb = min(kBandBlock, bands - blk * kBandBlock);
+    const int group = rem / nb;
+    return make_int2(blk * kBandBlock + (rem - group * nb), group);
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -111,19 +107,8 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
     const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
     const float* __restrict__ hp, float* __restrict__ eta_o, float* __restrict__ u_o,
     float* __restrict__ v_o, FoldPartial* __restrict__ part, StepGeometry geo, StepCoef k) {
-    const int tile = tile_of_block(blockIdx.x, geo.nblocks);
-#if SW2D_BAND_BLOCK > 1
-    // blocks of SW2D_BAND_BLOCK vertically adjacent bands are dispatched together
-    const int per_block = geo.groups_x * SW2D_BAND_BLOCK;
-    const int blk = tile / per_block;
-    const int rem = tile - blk * per_block;
-    const int nb = min(SW2D_BAND_BLOCK, geo.bands - blk * SW2D_BAND_BLOCK);
-    const int group = rem / nb;
-    const int band = blk * SW2D_BAND_BLOCK + (rem - group * nb);
-#else
-    const int band = tile / geo.groups_x;
-    const int group = tile - band * geo.groups_x;
-#endif
+    const int2 bg = band_and_group(blockIdx.x, geo.nblocks, geo.groups_x, geo.bands);
+    const int band = bg.x, group = bg.y;
     constexpr bool kAdv = (kVar & kVarAdvection) != 0;
     constexpr int kOut = kAdv ? kAdvStripOut : kStripOut;
     constexpr int kWest = kAdv ? kAdvHaloW : kHalo;
@@ -142,7 +127,6 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
         march_adv<kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k, f_disp,
                         f_mu, f_mv);
     } else if (strip < geo.strips) {
-#if SW2D_ZIGZAG
         // Odd bands march south, so each band boundary is read by both of its bands at
         // the same moment (both at their start or both at their end) and the second
         // read hits L2 instead of HBM.
@@ -150,7 +134,6 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_step_kernel(
             march<false, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1,
                                k, f_disp, f_mu, f_mv);
         else
-#endif
             march<true, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1,
                               k, f_disp, f_mu, f_mv);
     }
@@ -165,18 +148,8 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
     const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
     const float* __restrict__ hp, float* __restrict__ eta_o, float* __restrict__ u_o,
     float* __restrict__ v_o, FoldPartial* __restrict__ part, int stride, StepGeometry geo, StepCoef k) {
-    const int tile = tile_of_block(blockIdx.x, geo.nblocks);
-#if SW2D_BAND_BLOCK > 1
-    const int per_block = geo.groups_x * SW2D_BAND_BLOCK;
-    const int blk = tile / per_block;
-    const int rem = tile - blk * per_block;
-    const int nb = min(SW2D_BAND_BLOCK, geo.bands - blk * SW2D_BAND_BLOCK);
-    const int group = rem / nb;
-    const int band = blk * SW2D_BAND_BLOCK + (rem - group * nb);
-#else
-    const int band = tile / geo.groups_x;
-    const int group = tile - band * geo.groups_x;
-#endif
+    const int2 bg = band_and_group(blockIdx.x, geo.nblocks, geo.groups_x, geo.bands);
+    const int band = bg.x, group = bg.y;
     constexpr int kOut = kWave - 4 * K;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
@@ -189,12 +162,10 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
 
     LaneFolds F[K];
     if (strip < geo.strips) {
-#if SW2D_ZIGZAG
-        if (band & 1)
+        if (band & 1)  // odd bands march south
             marchK<K, false, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k,
                                    F);
         else
-#endif
             marchK<K, true, kVar>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c, col_in, out_lane, j0, j1, k,
                                   F);
     }
@@ -206,28 +177,14 @@ __global__ __launch_bounds__(kGroupThreads) void sw2d_stepk_kernel(
 }
 
 // The same with two adjacent columns per lane: strips of 128 - 4K owned columns; kWide when
-// nx is even (8-byte row accesses). The register budget is held to SW2D_PAIR_WAVES waves per
-// SIMD.
-#ifndef SW2D_PAIR_WAVES
-#define SW2D_PAIR_WAVES 3
-#endif
+// nx is even (8-byte row accesses). The register budget is held to 3 waves per SIMD.
 template <int K, bool kWide>
-__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(SW2D_PAIR_WAVES))) void sw2d_stepk_pair_kernel(
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(3))) void sw2d_stepk_pair_kernel(
     const float* __restrict__ eta, const float* __restrict__ u, const float* __restrict__ v,
     const float* __restrict__ hp, float* __restrict__ eta_o, float* __restrict__ u_o,
     float* __restrict__ v_o, FoldPartial* __restrict__ part, int stride, StepGeometry geo, StepCoef k) {
-    const int tile = tile_of_block(blockIdx.x, geo.nblocks);
-#if SW2D_BAND_BLOCK > 1
-    const int per_block = geo.groups_x * SW2D_BAND_BLOCK;
-    const int blk = tile / per_block;
-    const int rem = tile - blk * per_block;
-    const int nb = min(SW2D_BAND_BLOCK, geo.bands - blk * SW2D_BAND_BLOCK);
-    const int group = rem / nb;
-    const int band = blk * SW2D_BAND_BLOCK + (rem - group * nb);
-#else
-    const int band = tile / geo.groups_x;
-    const int group = tile - band * geo.groups_x;
-#endif
+    const int2 bg = band_and_group(blockIdx.x, geo.nblocks, geo.groups_x, geo.bands);
+    const int band = bg.x, group = bg.y;
     constexpr int kOut = 2 * kWave - 4 * K;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
@@ -240,12 +197,10 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(S
 
     LaneFolds F[K];
     if (strip < geo.strips) {
-#if SW2D_ZIGZAG
-        if (band & 1)
+        if (band & 1)  // odd bands march south
             marchK_pair<K, false, kWide>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c0, col_in, owned, j0, j1,
                                          k, F);
         else
-#endif
             marchK_pair<K, true, kWide>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c0, col_in, owned, j0, j1,
                                         k, F);
     }
@@ -416,7 +371,6 @@ hipError_t launch_stepk(int K, int kvar, const float* eta, const float* u, const
 #undef SW2D_VARK_CASE
         return hipErrorInvalidValue;
     }
-#if SW2D_PAIR_COLUMNS
     const bool wide = (geo.nx % 2) == 0;
 #define SW2D_PAIR_CASE(KK)                                                                                         \
     case KK:                                                                                                       \
@@ -435,24 +389,6 @@ hipError_t launch_stepk(int K, int kvar, const float* eta, const float* u, const
             return hipErrorInvalidValue;
     }
 #undef SW2D_PAIR_CASE
-    return hipGetLastError();
-#endif
-    switch (K) {
-        case 2:
-            hipLaunchKernelGGL(sw2d_stepk_kernel<2>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, stride,
-                               geo, k);
-            break;
-        case 3:
-            hipLaunchKernelGGL(sw2d_stepk_kernel<3>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, stride,
-                               geo, k);
-            break;
-        case 4:
-            hipLaunchKernelGGL(sw2d_stepk_kernel<4>, grid, block, 0, s, eta, u, v, hp, eta_o, u_o, v_o, part, stride,
-                               geo, k);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 

@@ -112,7 +112,6 @@ struct PairStage {
     }
 };
 
-#if SW2D_BUFFER_IO
 // Rows of a column pair. kWide: nx is even, so a pair never straddles the end of a row and
 // one 8-byte load or store moves it; otherwise each column goes through its own 4-byte
 // access, and a b column past the row end reads 0 and is not written.
@@ -157,7 +156,7 @@ __device__ __forceinline__ void marchK_pair(const float* __restrict__ eta, const
                                             float* __restrict__ v_o, int nx, int ny, int c0, bool col_in,
                                             bool owned, int j0, int j1, const StepCoef& k, LaneFolds* F) {
     constexpr int step = kNorth ? 1 : -1;
-    constexpr int P = SW2D_PREFETCH;
+    constexpr int P = kRowsAhead;
     const int r_first = kNorth ? j0 - 2 * K : j1 + 2 * K - 1;
     const int n_rows = j1 - j0 + 4 * K;
     const PairIO<kWide> io{nx, ny, col_in ? (unsigned)c0 * 4u : kNoLane};
@@ -242,6 +241,5 @@ __device__ __forceinline__ void marchK_pair(const float* __restrict__ eta, const
     }
     if (i < n_rows) row(i, std::true_type{});
 }
-#endif
 
 }  // namespace sw2d

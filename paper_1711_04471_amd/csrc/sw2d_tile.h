@@ -11,54 +11,15 @@
 
 namespace sw2d {
 
-#ifndef SW2D_PREFETCH
-#define SW2D_PREFETCH 1
-#endif
-#ifndef SW2D_DPP
-#define SW2D_DPP 1
-#endif
-#ifndef SW2D_NT_STORE
-#define SW2D_NT_STORE 0
-#endif
-#ifndef SW2D_XCD_MAP
-#define SW2D_XCD_MAP 1
-#endif
-#ifndef SW2D_ZIGZAG
-#define SW2D_ZIGZAG 1
-#endif
-#ifndef SW2D_BAND_BLOCK
-#define SW2D_BAND_BLOCK 2
-#endif
-#ifndef SW2D_BUFFER_IO
-#define SW2D_BUFFER_IO 1
-#endif
-static_assert(SW2D_PREFETCH >= 1 && SW2D_PREFETCH <= 4, "prefetch depth");
-
 // Lane l receives lane l+1's value (its east neighbour); lane 63 receives 0 (the DPP
 // bound control writes zero where the source lane lies outside the wave).
 __device__ __forceinline__ float from_east(float x) {
-#if SW2D_DPP
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
-#else
-    return __shfl_down(x, 1, kWave);
-#endif
 }
 
 // Lane l receives lane l-1's value (its west neighbour); lane 0 receives 0.
 __device__ __forceinline__ float from_west(float x) {
-#if SW2D_DPP
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138 /* wave_shr:1 */, 0xf, 0xf, true));
-#else
-    return __shfl_up(x, 1, kWave);
-#endif
-}
-
-__device__ __forceinline__ void store(float* p, float x) {
-#if SW2D_NT_STORE
-    __builtin_nontemporal_store(x, p);
-#else
-    *p = x;
-#endif
 }
 
 // Formulas of the plain step (Sect. 6.2), written once and used by every row pipeline
@@ -430,7 +391,6 @@ struct StageAdv {
     }
 };
 
-#if SW2D_BUFFER_IO
 // Rows go through buffer resources: one per field and row, whose size is the row's bytes,
 // or zero for a row outside the grid. The hardware returns 0 for a load outside the
 // resource and drops a store there, so a lane outside the grid (its byte offset, taken
@@ -453,9 +413,11 @@ __device__ __forceinline__ float row_load(const float* base, int r, int nx, int 
 __device__ __forceinline__ void row_store(float* base, int r, int nx, unsigned off, float x) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), row_rsrc(base, r, nx, r + 1), (int)off, 0, 0);
 }
-#endif
 
-// Loads rows of one lane's column through a prefetch queue of SW2D_PREFETCH rows.
+// Rows requested ahead of the one being processed (deeper queues measured no faster).
+constexpr int kRowsAhead = 1;
+
+// Loads rows of one lane's column through a queue of kRowsAhead rows.
 struct RowLoader {
     const float* __restrict__ eta;
     const float* __restrict__ u;
@@ -463,20 +425,14 @@ struct RowLoader {
     const float* __restrict__ hp;
     int nx, ny, c;
     bool col_in;
-    float qe[SW2D_PREFETCH], qh[SW2D_PREFETCH], qu[SW2D_PREFETCH], qv[SW2D_PREFETCH];
+    float qe[kRowsAhead], qh[kRowsAhead], qu[kRowsAhead], qv[kRowsAhead];
 
-#if SW2D_BUFFER_IO
     __device__ __forceinline__ float load(const float* __restrict__ p, int r) const {
         return row_load(p, r, nx, ny, col_in ? (unsigned)c * 4u : kNoLane);
     }
-#else
-    __device__ __forceinline__ float load(const float* __restrict__ p, int r) const {
-        return (col_in && r >= 0 && r < ny) ? p[(size_t)r * nx + c] : 0.f;
-    }
-#endif
     __device__ __forceinline__ void fill(int r_first, int step, int n_rows) {
 #pragma unroll
-        for (int d = 0; d < SW2D_PREFETCH; ++d) {
+        for (int d = 0; d < kRowsAhead; ++d) {
             const int rr = r_first + d * step;
             const bool ok = d < n_rows;
             qe[d] = ok ? load(eta, rr) : 0.f;
@@ -485,7 +441,7 @@ struct RowLoader {
             qv[d] = ok ? load(v, rr) : 0.f;
         }
     }
-    // Row i (at r) out of the queue; row i + SW2D_PREFETCH requested.
+    // Row i (at r) out of the queue; row i + kRowsAhead requested.
     __device__ __forceinline__ void next(int i, int r, int step, int n_rows, float& e, float& h, float& uu,
                                          float& vv) {
         e = qe[0];
@@ -493,18 +449,18 @@ struct RowLoader {
         uu = qu[0];
         vv = qv[0];
 #pragma unroll
-        for (int d = 0; d + 1 < SW2D_PREFETCH; ++d) {
+        for (int d = 0; d + 1 < kRowsAhead; ++d) {
             qe[d] = qe[d + 1];
             qh[d] = qh[d + 1];
             qu[d] = qu[d + 1];
             qv[d] = qv[d + 1];
         }
-        if (i + SW2D_PREFETCH < n_rows) {
-            const int rr = r + SW2D_PREFETCH * step;
-            qe[SW2D_PREFETCH - 1] = load(eta, rr);
-            qh[SW2D_PREFETCH - 1] = load(hp, rr);
-            qu[SW2D_PREFETCH - 1] = load(u, rr);
-            qv[SW2D_PREFETCH - 1] = load(v, rr);
+        if (i + kRowsAhead < n_rows) {
+            const int rr = r + kRowsAhead * step;
+            qe[kRowsAhead - 1] = load(eta, rr);
+            qh[kRowsAhead - 1] = load(hp, rr);
+            qu[kRowsAhead - 1] = load(u, rr);
+            qv[kRowsAhead - 1] = load(v, rr);
         }
     }
 };
@@ -516,23 +472,12 @@ struct RowStorer {
     float* __restrict__ v;
     int nx, c;
     bool out_lane;
-#if SW2D_BUFFER_IO
     __device__ __forceinline__ void put(int r, float e, float uu, float vv) const {
         const unsigned off = out_lane ? (unsigned)c * 4u : kNoLane;
         row_store(eta, r, nx, off, e);
         row_store(u, r, nx, off, uu);
         row_store(v, r, nx, off, vv);
     }
-#else
-    __device__ __forceinline__ void put(int r, float e, float uu, float vv) const {
-        if (out_lane) {
-            const size_t o = (size_t)r * nx + c;
-            store(eta + o, e);
-            store(u + o, uu);
-            store(v + o, vv);
-        }
-    }
-#endif
 };
 
 // Folds of one step over this lane's owned cells.
