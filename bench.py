@@ -39,6 +39,14 @@ FLOP_PER_CELL_STEP = 33
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # MI355X's published FP32 vector peak (counts packed two-wide FMAs)
 VALU_PEAK_PUBLISHED_TFLOPS = 157.3
+# dense BF16 matrix-core peak (no sparsity)
+BF16_PEAK_TFLOPS = 2500.0
+# the network's arithmetic per coarse cell with its real channel counts (5-32-32-32-3, 3x3):
+# forward 2 * 9 * (5*32 + 32*32 + 32*32 + 32*3); weight gradient the same; data gradient of
+# layers 2-4 only (the input needs none)
+CNN_FWD_FLOP_PER_CELL = 2 * 9 * (5 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
+CNN_WGRAD_FLOP_PER_CELL = CNN_FWD_FLOP_PER_CELL
+CNN_DGRAD_FLOP_PER_CELL = 2 * 9 * (32 * 32 + 32 * 32 + 32 * 3)
 # timed repetitions of the headline measurement; value comes from the median
 REPS = 5
 
@@ -290,6 +298,77 @@ def batched_leg(steps, warmup, log):
     }
 
 
+def cnn_timings(net, trainer, case):
+    """Kernel times of the network (HIP events on the stream the library launches on) and
+    their fraction of the dense BF16 peak, counted on the method's own arithmetic (real
+    channel counts, not the padded 16/32 the kernels compute): the one-kernel forward on one
+    coarse image, the weight gradient of a 32 -> 32 layer on the training minibatch, and one
+    whole minibatch of training (forward chain, loss, data and weight gradients, Adam)."""
+    import ctypes
+
+    import torch
+
+    from paper_1711_04471_amd import _lib
+    from paper_1711_04471_amd import surrogate as S
+    from paper_1711_04471_amd.sw2d import Sw2d
+
+    lib = _lib.load()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    out = {}
+    with Sw2d.from_case(case) as fine:
+        co = S.Coarse(fine, case)
+        mean_a, mp = S._fptr(net.stats.in_mean)
+        std_a, sp = S._fptr(net.stats.in_std)
+        e, u, v = co.sim.state()
+        ms = timed(lambda: net.forward_fused(e, u, v, co.H, co.mask, co.ny, co.nx, mp, sp), 50)
+        cells = co.nx * co.ny
+        tf = cells * CNN_FWD_FLOP_PER_CELL / (ms * 1e-3) / 1e12
+        out["forward"] = {"kernel": "cnn_fused_kernel", "image": f"{co.nx}x{co.ny}", "ms": round(ms, 4),
+                          "flop_per_cell": CNN_FWD_FLOP_PER_CELL, "achieved_tflops": round(tf, 1),
+                          "peak_tflops": BF16_PEAK_TFLOPS, "frac": round(tf / BF16_PEAK_TFLOPS, 4)}
+        co.sim.close()
+    n, h, w = trainer.batch, trainer.ny, trainer.nx
+    _, acts, _, dz = net._buffers(n, h, w)
+    gw, gb = net.weight(1, "grad")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    s = net.stream()
+    ms = timed(lambda: lib.sw2d_conv3x3_wgrad(p(acts[0]), 32, p(dz[0]), n, h, w, p(gw), p(gb), p(trainer.work),
+                                              trainer.work.numel(), s), 20)
+    flop = n * h * w * 2 * 9 * 32 * 32
+    tf = flop / (ms * 1e-3) / 1e12
+    out["wgrad_32"] = {"kernel": "wgrad_kernel<32> + wgrad_reduce_kernel", "minibatch": f"{n}x{w}x{h}",
+                       "ms": round(ms, 4), "achieved_tflops": round(tf, 1), "peak_tflops": BF16_PEAK_TFLOPS,
+                       "frac": round(tf / BF16_PEAK_TFLOPS, 4)}
+    idx = list(range(n))
+
+    def train_step():
+        trainer.step(idx)
+        net.adam(lr=0.0)
+
+    ms = timed(train_step, 20)
+    flop = n * h * w * (CNN_FWD_FLOP_PER_CELL + CNN_WGRAD_FLOP_PER_CELL + CNN_DGRAD_FLOP_PER_CELL)
+    tf = flop / (ms * 1e-3) / 1e12
+    out["train_minibatch"] = {"minibatch": f"{n}x{w}x{h}", "ms": round(ms, 4),
+                              "flop_per_cell": CNN_FWD_FLOP_PER_CELL + CNN_WGRAD_FLOP_PER_CELL
+                              + CNN_DGRAD_FLOP_PER_CELL,
+                              "achieved_tflops": round(tf, 1), "peak_tflops": BF16_PEAK_TFLOPS,
+                              "frac": round(tf / BF16_PEAK_TFLOPS, 4),
+                              "note": "forward chain, masked loss, data and weight gradients and Adam "
+                                      "(learning rate 0, so the weights stay as trained)"}
+    return out
+
+
 def surrogate_leg(args, log):
     """The learned coarse-step surrogate: 4x-coarsened state, coarse step of 4 dt plus the
     CNN correction, trained on snapshot pairs of plain fine runs (seeds 50000+); rollouts
@@ -309,11 +388,14 @@ def surrogate_leg(args, log):
     net = S.ConvNet(seed=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hist = S.Trainer(net, ds, batch=4, noise=0.05).fit(epochs=args.surrogate_epochs, lr=2e-3)
+    trainer = S.Trainer(net, ds, batch=4, noise=0.05)
+    hist = trainer.fit(epochs=args.surrogate_epochs, lr=2e-3)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     samples = ds.samples
-    del ds
+    cnn = cnn_timings(net, trainer, S.fine_basin(50200, n))
+    log(f"cnn kernels: {cnn}")
+    del trainer, ds
     torch.cuda.empty_cache()
     log(f"surrogate training {train_s:.1f} s, loss {hist}")
     n_coarse, judge, thr = N_COARSE, JUDGE_EVERY, THRESHOLD
@@ -378,7 +460,7 @@ def surrogate_leg(args, log):
         "mean_rmse_coarse_only": float(np.mean([x for p in per for x in p["rmse_coarse_only"]])),
         "nonfinite_judges_cnn": int(sum(not np.isfinite(x) for p in per for x in p["rmse_cnn"])),
         "nonfinite_judges_coarse_only": int(sum(not np.isfinite(x) for p in per for x in p["rmse_coarse_only"])),
-        "train_s": round(train_s, 2), "dataset_s": round(gen_s, 2), "per_seed": per,
+        "train_s": round(train_s, 2), "dataset_s": round(gen_s, 2), "cnn_roofline": cnn, "per_seed": per,
     }
 
 

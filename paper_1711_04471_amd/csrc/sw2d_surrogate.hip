@@ -527,85 +527,168 @@ __global__ __launch_bounds__(kFuThreads) void cnn_fused_kernel(RawIn raw, InputN
 }
 
 // ------------------------------------------------------------------------------ wgrad
-// Split over pixel chunks: workgroup g takes tiles g*kWgTiles ... of all images' 4 x 64
-// pixel tiles; each wave accumulates one row of the tile for all 9 taps (9 accumulators
-// of 32 x 32), the four waves are added in LDS in wave order, and the chunk's partial
-// [9][32][KIN] (and the bias partial [32]) goes to global memory.
-constexpr int kWgTH = 4;
-constexpr int kWgTW = 64;
-constexpr int kWgTiles = 16;
+// dW[t][o][c] = sum_p dY[p][o] X[p + off_t][c] on the MFMA with K = pixels: A = dY (32
+// outputs x 16 pixels), B = X shifted by the tap (16 pixels x 32 channels). Both operands
+// take 8 consecutive pixels of one channel per lane while the maps are NHWC (channels
+// contiguous), so a tile is staged in LDS pair-packed: a dword holds two horizontally
+// adjacent pixels of one channel, dword (r * pairs + q) * 32 + c for row r, pair q,
+// channel c. A lane reads one row's pixels c0 - 1 .. c0 + 8 of its channel as 5 dwords and
+// forms the three horizontal taps' operands from them (the odd tap by byte alignment); the
+// dY operand is 4 dwords. Workgroup g takes tiles g * kWgTiles ... of all images' 4 x 64
+// pixel tiles, fetching the next tile into registers while the current one is multiplied;
+// each wave accumulates one row of the tile for all 9 taps (9 accumulators of 32 x 32),
+// the four waves are added in LDS in wave order, and the chunk's partial [9][32][KIN] (and
+// the bias partial [32]) goes to global memory.
+constexpr int kWgTH = 4;                    // rows per tile, one per wave
+constexpr int kWgTW = 64;                   // pixels per tile row
+constexpr int kWgTiles = 16;                // tiles per chunk
+constexpr int kWgXPairs = (kWgTW + 2) / 2;  // pairs of the input rows: pixels -1 .. kWgTW
+constexpr int kWgDPairs = kWgTW / 2;        // pairs of the dY rows
+constexpr int kWgXRows = kWgTH + 2;
+constexpr int kWgXItems = kWgXRows * kWgXPairs * 4;  // (row, pair, 8-channel group), 32 channels
+constexpr int kWgDItems = kWgTH * kWgDPairs * 4;
+constexpr int kWgXPer = (kWgXItems + 255) / 256;
+constexpr int kWgDPer = (kWgDItems + 255) / 256;
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Channels 2m, 2m+1 of pixels p0 (x) and p1 (y) -> dwords (p0 c, p1 c) for c = 2m and 2m+1.
+__device__ __forceinline__ void pair_pack(const uint4& x, const uint4& y, uint4& lo, uint4& hi) {
+    lo.x = __builtin_amdgcn_perm(y.x, x.x, 0x05040100u);
+    lo.y = __builtin_amdgcn_perm(y.x, x.x, 0x07060302u);
+    lo.z = __builtin_amdgcn_perm(y.y, x.y, 0x05040100u);
+    lo.w = __builtin_amdgcn_perm(y.y, x.y, 0x07060302u);
+    hi.x = __builtin_amdgcn_perm(y.z, x.z, 0x05040100u);
+    hi.y = __builtin_amdgcn_perm(y.z, x.z, 0x07060302u);
+    hi.z = __builtin_amdgcn_perm(y.w, x.w, 0x05040100u);
+    hi.w = __builtin_amdgcn_perm(y.w, x.w, 0x07060302u);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(unsigned a, unsigned b, unsigned c, unsigned d) {
+    return __builtin_bit_cast(bf16x8, (u32x4){a, b, c, d});
+}
 
 template <int KIN>
 __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
                                                     int nimg, int H, int W, float* __restrict__ part_w,
                                                     float* __restrict__ part_b) {
-    constexpr int kXRows = kWgTH + 2, kXCols = kWgTW + 2;
-    __shared__ __attribute__((aligned(16))) uint16_t xs[kXRows * kXCols * KIN];
-    __shared__ __attribute__((aligned(16))) uint16_t ds[kWgTH * kWgTW * 32];
-    __shared__ float red[4][32];
+    constexpr int G = KIN / 8;  // 8-channel groups of the input map
+    __shared__ __attribute__((aligned(16))) unsigned xs[kWgXRows * kWgXPairs * 32];
+    __shared__ __attribute__((aligned(16))) unsigned ds[kWgTH * kWgDPairs * 32];
+    __shared__ float red[4][2][32];
     __shared__ float tapsum[32 * 32];
     const int tiles_x = (W + kWgTW - 1) / kWgTW, tiles_y = (H + kWgTH - 1) / kWgTH;
     const int tiles = tiles_x * tiles_y * nimg;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int half = lane / 32, j = lane % 32;
+    const int first = blockIdx.x * kWgTiles;
+    const int ntiles = min(kWgTiles, tiles - first);
+
+    if constexpr (KIN < 32) {
+        // channels KIN .. 31 of the input rows stay zero: they are the B columns j >= KIN
+        for (int e = threadIdx.x; e < kWgXRows * kWgXPairs * 32; e += 256)
+            if (e % 32 >= KIN) xs[e] = 0u;
+    }
+
+    // the tile's rows in registers: input items (row, pair, group) and dY items
+    uint4 rx[kWgXPer][2], rd[kWgDPer][2];
+    auto fetch = [&](int k) {
+        const int tile = first + k;
+        const int img = tile / (tiles_x * tiles_y);
+        const int tt = tile - img * tiles_x * tiles_y;
+        const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
+        const int y0 = ty * kWgTH, x0 = tx * kWgTW;
+        const size_t img_off = (size_t)img * H * W;
+#pragma unroll
+        for (int i = 0; i < kWgXPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int g = e % 4, rq = e / 4;
+            const int r = rq / kWgXPairs, q = rq - r * kWgXPairs;
+            const int gy = y0 - 1 + r, gx = x0 - 1 + 2 * q;
+            const bool row_ok = e < kWgXItems && g < G && gy >= 0 && gy < H;
+            const uint4* src = reinterpret_cast<const uint4*>(x + (img_off + (size_t)gy * W + gx) * KIN) + g;
+            rx[i][0] = (row_ok && gx >= 0 && gx < W) ? src[0] : make_uint4(0u, 0u, 0u, 0u);
+            rx[i][1] = (row_ok && gx + 1 < W) ? src[G] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < kWgDPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int g = e % 4, rq = e / 4;
+            const int r = rq / kWgDPairs, q = rq - r * kWgDPairs;
+            const int gy = y0 + r, gx = x0 + 2 * q;
+            const bool row_ok = e < kWgDItems && gy < H;
+            const uint4* src = reinterpret_cast<const uint4*>(dy + (img_off + (size_t)gy * W + gx) * 32) + g;
+            rd[i][0] = (row_ok && gx < W) ? src[0] : make_uint4(0u, 0u, 0u, 0u);
+            rd[i][1] = (row_ok && gx + 1 < W) ? src[4] : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int i = 0; i < kWgXPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int g = e % 4, rq = e / 4;
+            if (e < kWgXItems && g < G) {
+                uint4 lo, hi;
+                pair_pack(rx[i][0], rx[i][1], lo, hi);
+                uint4* dst = reinterpret_cast<uint4*>(xs + rq * 32 + 8 * g);
+                dst[0] = lo;
+                dst[1] = hi;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kWgDPer; ++i) {
+            const int e = threadIdx.x + 256 * i;
+            const int g = e % 4, rq = e / 4;
+            if (e < kWgDItems) {
+                uint4 lo, hi;
+                pair_pack(rd[i][0], rd[i][1], lo, hi);
+                uint4* dst = reinterpret_cast<uint4*>(ds + rq * 32 + 8 * g);
+                dst[0] = lo;
+                dst[1] = hi;
+            }
+        }
+    };
 
     f32x16 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
-    float bsum = 0.f;  // bias gradient: thread (wave, j < 32) sums channel j of its row
+    float bsum = 0.f;  // bias gradient: channel j over this lane's pixels
 
-    for (int k = 0; k < kWgTiles; ++k) {
-        const int tile = blockIdx.x * kWgTiles + k;
-        if (tile >= tiles) break;
-        const int img = tile / (tiles_x * tiles_y);
-        const int tt = tile - img * tiles_x * tiles_y;
-        const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
-        const int y0 = ty * kWgTH, x0 = tx * kWgTW;
-        const size_t img_off = (size_t)img * H * W;
+    if (ntiles > 0) fetch(0);
+    for (int k = 0; k < ntiles; ++k) {
+        __syncthreads();  // every wave is done with the previous tile
+        stage();
         __syncthreads();
-        for (int e = threadIdx.x; e < kXRows * kXCols * (KIN / 8); e += 256) {
-            const int pix = e / (KIN / 8), ch = e - pix * (KIN / 8);
-            const int r = pix / kXCols, c = pix - r * kXCols;
-            const int gy = y0 + r - 1, gx = x0 + c - 1;
-            uint4 val = make_uint4(0u, 0u, 0u, 0u);
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-                val = reinterpret_cast<const uint4*>(x + (img_off + (size_t)gy * W + gx) * KIN)[ch];
-            reinterpret_cast<uint4*>(xs)[e] = val;
-        }
-        for (int e = threadIdx.x; e < kWgTH * kWgTW * 4; e += 256) {
-            const int pix = e / 4, ch = e - pix * 4;
-            const int r = pix / kWgTW, c = pix - r * kWgTW;
-            const int gy = y0 + r, gx = x0 + c;
-            uint4 val = make_uint4(0u, 0u, 0u, 0u);
-            if (gy < H && gx < W) val = reinterpret_cast<const uint4*>(dy + (img_off + (size_t)gy * W + gx) * 32)[ch];
-            reinterpret_cast<uint4*>(ds)[e] = val;
-        }
-        __syncthreads();
-        // bias gradient partial: channel j over this wave's row
-        if (half == 0)
-            for (int c = 0; c < kWgTW; ++c) bsum += bf2f(ds[(wave * kWgTW + c) * 32 + j]);
-        // K steps of 16 pixels along this wave's row
+        if (k + 1 < ntiles) fetch(k + 1);
+        // K steps of 16 pixels along this wave's row; lane: pixels c0 .. c0 + 7
 #pragma unroll 1
         for (int ks = 0; ks < kWgTW / 16; ++ks) {
-            const int c0 = ks * 16 + half * 8;  // first of this lane's 8 pixels
-            bf16x8 av;  // A[o = j][pixels c0..c0+7] from dY
+            const int q0 = ks * 8 + half * 4;  // pair of pixel c0 = 16 ks + 8 half
+            const unsigned* dq = ds + (wave * kWgDPairs + q0) * 32 + j;
+            const unsigned a0 = dq[0], a1 = dq[32], a2 = dq[64], a3 = dq[96];
+            const bf16x8 av = as_bf16x8(a0, a1, a2, a3);
+            bsum += __uint_as_float(a0 << 16);
+            bsum += __uint_as_float(a0 & 0xffff0000u);
+            bsum += __uint_as_float(a1 << 16);
+            bsum += __uint_as_float(a1 & 0xffff0000u);
+            bsum += __uint_as_float(a2 << 16);
+            bsum += __uint_as_float(a2 & 0xffff0000u);
+            bsum += __uint_as_float(a3 << 16);
+            bsum += __uint_as_float(a3 & 0xffff0000u);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = (short)ds[(wave * kWgTW + c0 + e) * 32 + j];
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int ky = t / 3, kx = t - 3 * (t / 3);
-                bf16x8 bv;  // B[pixels][c = j] from X shifted by the tap
-                if (j < KIN) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        bv[e] = (short)xs[((wave + ky) * kXCols + c0 + e + kx) * KIN + j];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) bv[e] = 0;
-                }
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+            for (int ky = 0; ky < 3; ++ky) {
+                // input pixels c0 - 1 .. c0 + 8 of row wave + ky - 1 (pairs q0 .. q0 + 4)
+                const unsigned* xq = xs + ((wave + ky) * kWgXPairs + q0) * 32 + j;
+                const unsigned d0 = xq[0], d1 = xq[32], d2 = xq[64], d3 = xq[96], d4 = xq[128];
+                const bf16x8 b0 = as_bf16x8(d0, d1, d2, d3);
+                const bf16x8 b1 = as_bf16x8(__builtin_amdgcn_alignbyte(d1, d0, 2), __builtin_amdgcn_alignbyte(d2, d1, 2),
+                                            __builtin_amdgcn_alignbyte(d3, d2, 2), __builtin_amdgcn_alignbyte(d4, d3, 2));
+                const bf16x8 b2 = as_bf16x8(d1, d2, d3, d4);
+                acc[3 * ky + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc[3 * ky + 0], 0, 0, 0);
+                acc[3 * ky + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc[3 * ky + 1], 0, 0, 0);
+                acc[3 * ky + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b2, acc[3 * ky + 2], 0, 0, 0);
             }
         }
     }
@@ -630,11 +713,14 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
             out[(size_t)t * 32 * KIN + e] = tapsum[o * 32 + c];
         }
     }
-    if (half == 0) red[wave][j] = bsum;
+    red[wave][half][j] = bsum;
     __syncthreads();
-    if (threadIdx.x < 32)
-        part_b[(size_t)blockIdx.x * 32 + threadIdx.x] =
-            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    if (threadIdx.x < 32) {
+        float b = 0.f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) b += red[w][0][threadIdx.x] + red[w][1][threadIdx.x];
+        part_b[(size_t)blockIdx.x * 32 + threadIdx.x] = b;
+    }
 }
 
 // dW[i] = sum over chunks of part[chunk][i], in a fixed order: a workgroup takes 32
