@@ -83,6 +83,13 @@ def parse():
     ap.add_argument("--no-sor", action="store_true", help="skip the SOR pressure-solver leg")
     ap.add_argument("--only-sor", action="store_true")
     ap.add_argument("--sor-solves", type=int, default=10)
+    ap.add_argument("--only-cnn", action="store_true",
+                    help="only the network kernels, timed with their initial weights (no dataset, no "
+                         "training: kernel times do not depend on the weights), for profiling")
+    ap.add_argument("--batched-rows", type=int, default=0,
+                    help="uniform band height for the batched leg instead of the autotuner's choice")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the batched leg's one-after-another comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device-to-device copy (the counter calibration)")
     args = ap.parse_args()
@@ -228,7 +235,7 @@ BATCH_PASS = 3  # steps per pass of the batched kernel
 BATCH_LAUNCH_PASSES = 16  # passes per persistent launch
 
 
-def batched_leg(steps, warmup, log):
+def batched_leg(steps, warmup, log, rows_uniform=0, sequential=True):
     """The 256-member ensemble (sides 128..1024, own bathymetry, mask, bumps and dt each)
     advanced by the persistent batched launch at BATCH_PASS steps per pass, against the same
     members stepped one after another through sw2d_step on the same GPU (at one step per
@@ -246,7 +253,10 @@ def batched_leg(steps, warmup, log):
     cases = inputs.ensemble(steps=steps)
     cells = sum(c.nx * c.ny for c in cases)
     cache = os.path.join(tempfile.gettempdir(), "sw2d_autotune.json")
-    rows = autotune.tune(cases, cache_path=cache, log=log, steps_per_pass=K, whole=True)
+    if rows_uniform:
+        rows = [rows_uniform] * len(cases)
+    else:
+        rows = autotune.tune(cases, cache_path=cache, log=log, steps_per_pass=K, whole=True)
     with Sw2dBatch(cases, band_rows=rows) as b:
         b.set_time_blocking(K)
         b.set_launch(steps_per_launch=BATCH_LAUNCH_PASSES * K, use_graph=True)
@@ -262,7 +272,7 @@ def batched_leg(steps, warmup, log):
         red = b.reduce()
     # the same members one after another through the single-grid path
     seqs = {}
-    for spp in (1, K):
+    for spp in ((1, K) if sequential else ()):
         sims = [Sw2d.from_case(c) for c in cases]
         for s in sims:
             if spp > 1:
@@ -276,16 +286,16 @@ def batched_leg(steps, warmup, log):
         seqs[spp] = time.perf_counter() - t0
         for s in sims:
             s.close()
-    seq = min(seqs.values())
+    seq = min(seqs.values()) if seqs else None
     return {
         "workload": f"ensemble_256: 256 basins, sides U{{128..1024}} (seed 4), members seed "
                     f"40000+k, 1-4 bumps, dx=500 m, own dt; {cells} cells in total",
         "steps": steps, "value": round(cells * steps / wall / 1e6, 1), "unit": "Mcell-steps/s",
         "ms_per_step": round(wall / steps * 1e3, 5),
         "steps_per_pass": K,
-        "sequential_value": round(cells * steps / seq / 1e6, 1),
-        "sequential_value_single_step": round(cells * steps / seqs[1] / 1e6, 1),
-        "speedup_vs_sequential": round(seq / wall, 2),
+        "sequential_value": round(cells * steps / seq / 1e6, 1) if seqs else None,
+        "sequential_value_single_step": round(cells * steps / seqs[1] / 1e6, 1) if seqs else None,
+        "speedup_vs_sequential": round(seq / wall, 2) if seqs else None,
         "roofline": {"bound": "hbm", "achieved": round(cells * BYTES_PER_CELL_STEP / K / (ev_ms * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(cells * BYTES_PER_CELL_STEP / K / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -299,6 +309,24 @@ def batched_leg(steps, warmup, log):
 
 
 def cnn_timings(net, trainer, case):
+    return _cnn_timings(net, trainer, case)
+
+
+def cnn_only_leg(n, log):
+    """The network kernels with their initial weights on a 1024^2 coarse image and a
+    4 x 1024^2 minibatch of restricted states: kernel time does not depend on the weights,
+    so no dataset generation or training runs (for profiling)."""
+    from paper_1711_04471_amd import surrogate as S
+
+    ds = S.make_dataset([50000], n=n, pairs_per_run=4, every=20, lead=20)
+    net = S.ConvNet(seed=1)
+    trainer = S.Trainer(net, ds, batch=4, noise=0.05)
+    out = _cnn_timings(net, trainer, S.fine_basin(50200, n))
+    log(f"cnn kernels: {out}")
+    return out
+
+
+def _cnn_timings(net, trainer, case):
     """Kernel times of the network (HIP events on the stream the library launches on) and
     their fraction of the dense BF16 peak, counted on the method's own arithmetic (real
     channel counts, not the padded 16/32 the kernels compute): the one-kernel forward on one
@@ -615,13 +643,17 @@ def main():
         return
     log = lambda m: print(f"# {m}", file=sys.stderr, flush=True)
     if args.only_batched:
-        print(json.dumps({"batched": batched_leg(args.batched_steps, args.warmup, log)}), flush=True)
+        print(json.dumps({"batched": batched_leg(args.batched_steps, args.warmup, log, args.batched_rows,
+                                                 not args.no_sequential)}), flush=True)
         return
     if args.only_surrogate:
         print(json.dumps({"surrogate": surrogate_leg(args, log)}), flush=True)
         return
     if args.only_sor:
         print(json.dumps({"sor": sor_leg(args, log)}), flush=True)
+        return
+    if args.only_cnn:
+        print(json.dumps({"cnn": cnn_only_leg(args.surrogate_fine, log)}), flush=True)
         return
     if args.only_basin2048:
         print(json.dumps({"basin_2048": basin2048_leg(1000, log)}), flush=True)
@@ -713,7 +745,7 @@ def main():
     if not args.no_variants:
         out["variants"] = variants_leg(case, min(args.steps, 200), log)
     if not args.no_batched:
-        out["batched"] = batched_leg(args.batched_steps, args.warmup, log)
+        out["batched"] = batched_leg(args.batched_steps, args.warmup, log, args.batched_rows, not args.no_sequential)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, log)
     if not args.no_sor:

@@ -260,7 +260,7 @@ class Coarse:
 @dataclass
 class Dataset:
     inputs: torch.Tensor   # FP32 [3][S][ny][nx]: restricted fine state (eta, u, v)
-    targets: torch.Tensor  # FP32 [3][S][ny][nx]: restricted fine 4 steps later minus one coarse step
+    targets: torch.Tensor  # FP32 [3][S][ny][nx]: restricted fine state lead = 4m fine steps later minus m coarse steps
     run_of: np.ndarray     # run index of each sample
     H: torch.Tensor        # FP32 [R][ny][nx]: coarse depth of each run
     mask: torch.Tensor     # uint8 [R][ny][nx]: coarse mask of each run

@@ -150,9 +150,9 @@ def test_fallback_policy(trained):
 
 def test_trained_network_gains_over_coarse_only(trained):
     """Held-out basins: eta RMSE after 20 coarse steps (80 fine) from the restricted fine
-    state, with the learned (damped) correction against the coarse model alone. Measured
-    when this bar was set: ratios 0.61-0.97, mean 0.82; beyond ~50 coarse steps the gain
-    fades (reported by the benchmark, not asserted here)."""
+    state, with the learned (damped) correction against the coarse model alone: below it on
+    every basin, and by 8 % on average. (The full configuration's gain at every checkpoint of
+    a whole rollout is asserted for the default network, which runs every fifth step.)"""
     net, _ = trained
     ratios = []
     for seed in (50200, 50201, 50202, 50203):
@@ -161,7 +161,7 @@ def test_trained_network_gains_over_coarse_only(trained):
         cnn = S.rollout(net, case, n_coarse=20, judge_every=20, threshold=1e9).rmse[0]
         ratios.append(cnn / base)
     print(json.dumps({"rmse_ratio_cnn_over_coarse": ratios}), flush=True)
-    assert np.mean(ratios) < 0.92 and max(ratios) < 1.05, ratios
+    assert np.mean(ratios) < 0.92 and max(ratios) < 1.0, ratios
 
 
 @pytest.fixture(scope="module")
@@ -213,3 +213,37 @@ def test_advance_equals_the_layer_by_layer_steps(trained):
     a.sim.close()
     b.sim.close()
     fine.close()
+
+
+FULL = 4096  # the full configuration: 4096^2 fine, 1024^2 coarse
+
+
+@pytest.fixture(scope="module")
+def trained_full():
+    """The benchmark's network: 2000 snapshot pairs from 20 plain 4096^2 runs (seeds
+    50000-50019), targets five coarse steps ahead, 18 epochs."""
+    ds = S.make_dataset([50000 + k for k in range(20)], n=FULL, pairs_per_run=100, every=20, lead=20)
+    net = S.ConvNet(seed=1)
+    S.Trainer(net, ds, batch=4, noise=0.05).fit(epochs=18, lr=2e-3)
+    del ds
+    torch.cuda.empty_cache()
+    return net
+
+
+def test_full_configuration_gains_at_every_checkpoint(trained_full):
+    """4096^2 fine -> 1024^2 coarse, the network before every fifth coarse step, 500 coarse
+    steps (2000 fine) judged every 50 with the threshold disabled, so that neither trajectory
+    is ever reset: on each held-out basin the eta RMSE with the learned correction is below
+    the coarse model's alone at every one of the 10 checkpoints."""
+    ratios = {}
+    for seed in (50200, 50201, 50202, 50203, 50204):
+        case = S.fine_basin(seed, FULL)
+        base = S.rollout(None, case, n_coarse=500, judge_every=50, threshold=1e9).rmse
+        cnn = S.rollout(trained_full, case, n_coarse=500, judge_every=50, threshold=1e9, correct_every=5).rmse
+        assert len(base) == len(cnn) == 10
+        assert np.all(np.isfinite(cnn)), cnn
+        ratios[seed] = [round(c / b, 3) for c, b in zip(cnn, base)]
+    print(json.dumps({"rmse_ratio_cnn_over_coarse_per_checkpoint": ratios}), flush=True)
+    allr = np.array(list(ratios.values()))
+    assert np.all(allr < 1.0), ratios
+    assert allr.mean() < 0.8, ratios
