@@ -130,7 +130,7 @@ def copy_probe(quiet=False):
 # band heights measured best per workload and steps per pass (sweeps in steps of 4 rows; the
 # throughput is a sawtooth in the band height, from how the last workgroups of a launch fill
 # the GPU)
-TUNED_ROWS = {("basin_8192", 1): 16, ("basin_8192", 2): 16, ("basin_8192", 3): 64, ("basin_8192", 4): 104,
+TUNED_ROWS = {("basin_8192", 1): 16, ("basin_8192", 2): 16, ("basin_8192", 3): 64, ("basin_8192", 4): 128,
               ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 24}
 
 

@@ -480,20 +480,19 @@ struct RowStorer {
     }
 };
 
-// Folds of one step over this lane's owned cells.
-// The maxima of |u| and |v| are kept as the bit patterns of the magnitudes, whose unsigned
-// order is the numeric order for non-negative floats: one AND and one integer max per value,
-// with no NaN canonicalisation (a NaN magnitude sorts above infinity and stays visible).
+// Folds of one step over this lane's owned cells. The maxima take the magnitude as a source
+// modifier of the float maximum (no separate instruction); a non-finite state shows in the
+// FP64 surface sum, which every non-finite velocity reaches in the same step.
 struct LaneFolds {
     double disp = 0.0;
-    unsigned mu_bits = 0u, mv_bits = 0u;
+    float max_u = 0.f, max_v = 0.f;
     __device__ __forceinline__ void add(float eta_new, float u_new, float v_new) {
         disp += (double)eta_new;  // zero on land
-        mu_bits = max(mu_bits, __float_as_uint(u_new) & 0x7fffffffu);
-        mv_bits = max(mv_bits, __float_as_uint(v_new) & 0x7fffffffu);
+        max_u = fmaxf(max_u, fabsf(u_new));
+        max_v = fmaxf(max_v, fabsf(v_new));
     }
-    __device__ __forceinline__ float mu() const { return __uint_as_float(mu_bits); }
-    __device__ __forceinline__ float mv() const { return __uint_as_float(mv_bits); }
+    __device__ __forceinline__ float mu() const { return max_u; }
+    __device__ __forceinline__ float mv() const { return max_v; }
 };
 
 // One wave marches a band [j0, j1) of its strip, north (kNorth) or south, and writes the
