@@ -534,21 +534,24 @@ __global__ __launch_bounds__(kFuThreads) void cnn_fused_kernel(RawIn raw, InputN
 // adjacent pixels of one channel, dword (r * pairs + q) * 32 + c for row r, pair q,
 // channel c. A lane reads one row's pixels c0 - 1 .. c0 + 8 of its channel as 5 dwords and
 // forms the three horizontal taps' operands from them (the odd tap by byte alignment); the
-// dY operand is 4 dwords. Workgroup g takes tiles g * kWgTiles ... of all images' 4 x 64
-// pixel tiles, fetching the next tile into registers while the current one is multiplied;
-// each wave accumulates one row of the tile for all 9 taps (9 accumulators of 32 x 32),
-// the four waves are added in LDS in wave order, and the chunk's partial [9][32][KIN] (and
-// the bias partial [32]) goes to global memory.
-constexpr int kWgTH = 4;                    // rows per tile, one per wave
-constexpr int kWgTW = 64;                   // pixels per tile row
-constexpr int kWgTiles = 16;                // tiles per chunk
+// dY operand is 4 dwords. Workgroup g takes tiles g * kWgTiles ... of all images' 4 x 128
+// pixel tiles, fetching the next tile into registers while the current one is multiplied.
+// Its 12 waves (3 per SIMD) split the work by tile row and tap row: wave w accumulates the
+// three taps of tap row ky = w / 4 over tile row w % 4 (3 accumulators of 32 x 32); the four
+// tile rows of a tap are added in LDS in row order, and the chunk's partial [9][32][KIN]
+// (and the bias partial [32]) goes to global memory.
+constexpr int kWgTH = 4;                    // rows per tile
+constexpr int kWgTW = 128;                  // pixels per tile row
+constexpr int kWgTiles = 8;                 // tiles per chunk
+constexpr int kWgWaves = 12;                // (tile row, tap row) pairs
+constexpr int kWgThreads = 64 * kWgWaves;
 constexpr int kWgXPairs = (kWgTW + 2) / 2;  // pairs of the input rows: pixels -1 .. kWgTW
 constexpr int kWgDPairs = kWgTW / 2;        // pairs of the dY rows
 constexpr int kWgXRows = kWgTH + 2;
 constexpr int kWgXItems = kWgXRows * kWgXPairs * 4;  // (row, pair, 8-channel group), 32 channels
 constexpr int kWgDItems = kWgTH * kWgDPairs * 4;
-constexpr int kWgXPer = (kWgXItems + 255) / 256;
-constexpr int kWgDPer = (kWgDItems + 255) / 256;
+constexpr int kWgXPer = (kWgXItems + kWgThreads - 1) / kWgThreads;
+constexpr int kWgDPer = (kWgDItems + kWgThreads - 1) / kWgThreads;
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
@@ -569,24 +572,25 @@ __device__ __forceinline__ bf16x8 as_bf16x8(unsigned a, unsigned b, unsigned c, 
 }
 
 template <int KIN>
-__global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
-                                                    int nimg, int H, int W, float* __restrict__ part_w,
-                                                    float* __restrict__ part_b) {
+__global__ __launch_bounds__(kWgThreads) void wgrad_kernel(const uint16_t* __restrict__ x,
+                                                           const uint16_t* __restrict__ dy, int nimg, int H, int W,
+                                                           float* __restrict__ part_w, float* __restrict__ part_b) {
     constexpr int G = KIN / 8;  // 8-channel groups of the input map
     __shared__ __attribute__((aligned(16))) unsigned xs[kWgXRows * kWgXPairs * 32];
     __shared__ __attribute__((aligned(16))) unsigned ds[kWgTH * kWgDPairs * 32];
-    __shared__ float red[4][2][32];
-    __shared__ float tapsum[32 * 32];
+    __shared__ float red[kWgTH][2][32];
+    __shared__ float tapsum[3][32 * 32];
     const int tiles_x = (W + kWgTW - 1) / kWgTW, tiles_y = (H + kWgTH - 1) / kWgTH;
     const int tiles = tiles_x * tiles_y * nimg;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int half = lane / 32, j = lane % 32;
+    const int row = wave % kWgTH, ky = wave / kWgTH;  // this wave's tile row and tap row
     const int first = blockIdx.x * kWgTiles;
     const int ntiles = min(kWgTiles, tiles - first);
 
     if constexpr (KIN < 32) {
         // channels KIN .. 31 of the input rows stay zero: they are the B columns j >= KIN
-        for (int e = threadIdx.x; e < kWgXRows * kWgXPairs * 32; e += 256)
+        for (int e = threadIdx.x; e < kWgXRows * kWgXPairs * 32; e += kWgThreads)
             if (e % 32 >= KIN) xs[e] = 0u;
     }
 
@@ -601,7 +605,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
         const size_t img_off = (size_t)img * H * W;
 #pragma unroll
         for (int i = 0; i < kWgXPer; ++i) {
-            const int e = threadIdx.x + 256 * i;
+            const int e = threadIdx.x + kWgThreads * i;
             const int g = e % 4, rq = e / 4;
             const int r = rq / kWgXPairs, q = rq - r * kWgXPairs;
             const int gy = y0 - 1 + r, gx = x0 - 1 + 2 * q;
@@ -612,7 +616,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
         }
 #pragma unroll
         for (int i = 0; i < kWgDPer; ++i) {
-            const int e = threadIdx.x + 256 * i;
+            const int e = threadIdx.x + kWgThreads * i;
             const int g = e % 4, rq = e / 4;
             const int r = rq / kWgDPairs, q = rq - r * kWgDPairs;
             const int gy = y0 + r, gx = x0 + 2 * q;
@@ -625,7 +629,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
     auto stage = [&]() {
 #pragma unroll
         for (int i = 0; i < kWgXPer; ++i) {
-            const int e = threadIdx.x + 256 * i;
+            const int e = threadIdx.x + kWgThreads * i;
             const int g = e % 4, rq = e / 4;
             if (e < kWgXItems && g < G) {
                 uint4 lo, hi;
@@ -637,7 +641,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
         }
 #pragma unroll
         for (int i = 0; i < kWgDPer; ++i) {
-            const int e = threadIdx.x + 256 * i;
+            const int e = threadIdx.x + kWgThreads * i;
             const int g = e % 4, rq = e / 4;
             if (e < kWgDItems) {
                 uint4 lo, hi;
@@ -649,12 +653,12 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
         }
     };
 
-    f32x16 acc[9];
+    f32x16 acc[3];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int t = 0; t < 3; ++t)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
-    float bsum = 0.f;  // bias gradient: channel j over this lane's pixels
+    float bsum = 0.f;  // bias gradient: channel j over this lane's pixels (tap row 0 only)
 
     if (ntiles > 0) fetch(0);
     for (int k = 0; k < ntiles; ++k) {
@@ -662,63 +666,65 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
         stage();
         __syncthreads();
         if (k + 1 < ntiles) fetch(k + 1);
-        // K steps of 16 pixels along this wave's row; lane: pixels c0 .. c0 + 7
-#pragma unroll 1
+        // K steps of 16 pixels along the tile row; lane: pixels c0 .. c0 + 7
+#pragma unroll 2
         for (int ks = 0; ks < kWgTW / 16; ++ks) {
             const int q0 = ks * 8 + half * 4;  // pair of pixel c0 = 16 ks + 8 half
-            const unsigned* dq = ds + (wave * kWgDPairs + q0) * 32 + j;
+            const unsigned* dq = ds + (row * kWgDPairs + q0) * 32 + j;
             const unsigned a0 = dq[0], a1 = dq[32], a2 = dq[64], a3 = dq[96];
+            // input pixels c0 - 1 .. c0 + 8 of image row row + ky - 1 (pairs q0 .. q0 + 4)
+            const unsigned* xq = xs + ((row + ky) * kWgXPairs + q0) * 32 + j;
+            const unsigned d0 = xq[0], d1 = xq[32], d2 = xq[64], d3 = xq[96], d4 = xq[128];
             const bf16x8 av = as_bf16x8(a0, a1, a2, a3);
-            bsum += __uint_as_float(a0 << 16);
-            bsum += __uint_as_float(a0 & 0xffff0000u);
-            bsum += __uint_as_float(a1 << 16);
-            bsum += __uint_as_float(a1 & 0xffff0000u);
-            bsum += __uint_as_float(a2 << 16);
-            bsum += __uint_as_float(a2 & 0xffff0000u);
-            bsum += __uint_as_float(a3 << 16);
-            bsum += __uint_as_float(a3 & 0xffff0000u);
-#pragma unroll
-            for (int ky = 0; ky < 3; ++ky) {
-                // input pixels c0 - 1 .. c0 + 8 of row wave + ky - 1 (pairs q0 .. q0 + 4)
-                const unsigned* xq = xs + ((wave + ky) * kWgXPairs + q0) * 32 + j;
-                const unsigned d0 = xq[0], d1 = xq[32], d2 = xq[64], d3 = xq[96], d4 = xq[128];
-                const bf16x8 b0 = as_bf16x8(d0, d1, d2, d3);
-                const bf16x8 b1 = as_bf16x8(__builtin_amdgcn_alignbyte(d1, d0, 2), __builtin_amdgcn_alignbyte(d2, d1, 2),
-                                            __builtin_amdgcn_alignbyte(d3, d2, 2), __builtin_amdgcn_alignbyte(d4, d3, 2));
-                const bf16x8 b2 = as_bf16x8(d1, d2, d3, d4);
-                acc[3 * ky + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc[3 * ky + 0], 0, 0, 0);
-                acc[3 * ky + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc[3 * ky + 1], 0, 0, 0);
-                acc[3 * ky + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b2, acc[3 * ky + 2], 0, 0, 0);
+            if (ky == 0) {
+                bsum += __uint_as_float(a0 << 16);
+                bsum += __uint_as_float(a0 & 0xffff0000u);
+                bsum += __uint_as_float(a1 << 16);
+                bsum += __uint_as_float(a1 & 0xffff0000u);
+                bsum += __uint_as_float(a2 << 16);
+                bsum += __uint_as_float(a2 & 0xffff0000u);
+                bsum += __uint_as_float(a3 << 16);
+                bsum += __uint_as_float(a3 & 0xffff0000u);
             }
+            const bf16x8 b0 = as_bf16x8(d0, d1, d2, d3);
+            const bf16x8 b1 = as_bf16x8(__builtin_amdgcn_alignbyte(d1, d0, 2), __builtin_amdgcn_alignbyte(d2, d1, 2),
+                                        __builtin_amdgcn_alignbyte(d3, d2, 2), __builtin_amdgcn_alignbyte(d4, d3, 2));
+            const bf16x8 b2 = as_bf16x8(d1, d2, d3, d4);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b2, acc[2], 0, 0, 0);
         }
     }
-    // add the four waves in wave order through LDS and write the chunk partial
+    // for each horizontal tap kx: the four tile rows of every tap row added in row order in
+    // LDS, then the three taps 3 ky + kx written out
     float* out = part_w + (size_t)blockIdx.x * 9 * 32 * KIN;
-    for (int t = 0; t < 9; ++t) {
-        __syncthreads();
-        // acc[t][e]: o = 8 (e / 4) + 4 half + e % 4, c = j
-        for (int w = 0; w < 4; ++w) {
-            if (wave == w) {
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+        for (int r = 0; r < kWgTH; ++r) {
+            __syncthreads();
+            if (row == r) {
+                // acc[kx][e]: o = 8 (e / 4) + 4 half + e % 4, c = j
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const int o = 8 * (e / 4) + 4 * half + (e % 4);
-                    if (w == 0) tapsum[o * 32 + j] = acc[t][e];
-                    else tapsum[o * 32 + j] += acc[t][e];
+                    if (r == 0) tapsum[ky][o * 32 + j] = acc[kx][e];
+                    else tapsum[ky][o * 32 + j] += acc[kx][e];
                 }
             }
-            __syncthreads();
         }
-        for (int e = threadIdx.x; e < 32 * KIN; e += 256) {
-            const int o = e / KIN, c = e - o * KIN;
-            out[(size_t)t * 32 * KIN + e] = tapsum[o * 32 + c];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * 32 * KIN; e += kWgThreads) {
+            const int yy = e / (32 * KIN), rem = e - yy * 32 * KIN;
+            const int o = rem / KIN, c = rem - o * KIN;
+            out[(size_t)(3 * yy + kx) * 32 * KIN + rem] = tapsum[yy][o * 32 + c];
         }
     }
-    red[wave][half][j] = bsum;
+    if (ky == 0) red[row][half][j] = bsum;
     __syncthreads();
     if (threadIdx.x < 32) {
         float b = 0.f;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) b += red[w][0][threadIdx.x] + red[w][1][threadIdx.x];
+        for (int r = 0; r < kWgTH; ++r) b += red[r][0][threadIdx.x] + red[r][1][threadIdx.x];
         part_b[(size_t)blockIdx.x * 32 + threadIdx.x] = b;
     }
 }
@@ -1060,9 +1066,9 @@ hipError_t launch_wgrad(int kin, const uint16_t* x, const uint16_t* dy, int nimg
                         float* part_b, float* dW, float* db, hipStream_t s) {
     const int chunks = wgrad_chunks(nimg, H, W);
     if (kin == 16)
-        hipLaunchKernelGGL(wgrad_kernel<16>, dim3(chunks), dim3(256), 0, s, x, dy, nimg, H, W, part_w, part_b);
+        hipLaunchKernelGGL(wgrad_kernel<16>, dim3(chunks), dim3(kWgThreads), 0, s, x, dy, nimg, H, W, part_w, part_b);
     else if (kin == 32)
-        hipLaunchKernelGGL(wgrad_kernel<32>, dim3(chunks), dim3(256), 0, s, x, dy, nimg, H, W, part_w, part_b);
+        hipLaunchKernelGGL(wgrad_kernel<32>, dim3(chunks), dim3(kWgThreads), 0, s, x, dy, nimg, H, W, part_w, part_b);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
