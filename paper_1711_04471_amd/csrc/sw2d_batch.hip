@@ -3,19 +3,20 @@
 //
 // Work list: every (instance, band, group of 4 strips) is one tile for one workgroup, as
 // in the single-grid kernel (same tile routine, so each instance is bitwise equal to the
-// same basin stepped alone). Tiles are ordered instance by instance in blocks of two
-// vertically adjacent bands, and workgroups take them round robin in an XCD-contiguous
-// order, so the workgroups running together cover a compact region.
+// same basin stepped alone). Tiles are listed instance by instance in blocks of two
+// vertically adjacent bands and handed out costliest first: each workgroup takes the next
+// tile from a work ticket (one atomic per tile) until the pass's tiles run out, so a
+// workgroup that finishes early takes more and the grid reaches the barrier together.
 //
-// Per step: workgroups process their tiles and write one fold partial per tile, then the
-// grid meets at a barrier. After the barrier, workgroup b adds the partials of instances
+// Per pass: workgroups process tiles and write one fold partial per tile and step, then the
+// grid meets at a barrier, where workgroup 0 also rewinds the ticket of the next pass. After the barrier, workgroup b adds the partials of instances
 // b, b+G, ... in a fixed order and writes their folds to the ring, then goes on with the
 // next step.
 //
 // The barrier uses no contended atomics: every workgroup publishes the epoch it has
 // reached in its own flag (after an agent-scope release), workgroup 0 waits for all
 // flags in parallel and publishes the epoch in one "go" word, which the others poll.
-// Epochs are the global step counts, so they only grow and nothing is ever reset. Every
+// Epochs are the global step counts, so they only grow and no flag is ever reset. Every
 // wait has a wall-clock deadline: on expiry it raises an error flag and the kernel
 // returns, so no wave can wait forever even if the grid were not co-resident.
 //
@@ -27,9 +28,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <functional>
 #include <new>
-#include <queue>
 #include <utility>
 #include <vector>
 
@@ -62,8 +61,6 @@ struct alignas(16) BatchTile {
 };
 static_assert(sizeof(BatchTile) == 128, "tile descriptor size");
 
-constexpr int kLdsTiles = 64;  // descriptors a workgroup keeps in LDS at a time
-
 constexpr int kFlagStride = 16;  // 64-bit words between flags: one 128 B line each
 
 struct BatchControl {
@@ -71,7 +68,8 @@ struct BatchControl {
     unsigned pad0;
     long long steps_done;   // advanced by the kernel at the end of every launch
     long long passes_done;  // passes over the state so far: its parity picks the current buffer
-    long long pad1[kFlagStride - 3];
+    unsigned next_tile[2];  // work tickets of the passes of each parity (position in the order)
+    long long pad1[kFlagStride - 4];
     unsigned long long go;  // last epoch every workgroup has reached (own line)
     unsigned long long pad2[kFlagStride - 1];
     // followed by one flag line per workgroup
@@ -89,8 +87,7 @@ constexpr int kBatchRing = 64;  // steps of per-instance folds kept
 struct BatchArgs {
     const BatchInst* inst;
     const BatchTile* tiles;
-    const int* order;      // tile ids grouped by workgroup
-    const int2* wg_range;  // [grid]: first position in order, tile count
+    const int* order;      // tile ids, costliest first: the order in which tiles are handed out
     FoldPartial* part;  // [2][K][n_tiles]
     sw2d_red* ring;     // [kBatchRing][n_inst]
     BatchControl* ctl;
@@ -111,8 +108,10 @@ __device__ __forceinline__ bool spin_until(const unsigned long long* word, unsig
     return true;
 }
 
-// Returns false (for the whole workgroup) if a wait ran past the deadline.
-__device__ bool grid_barrier(const BatchArgs& a, unsigned long long epoch) {
+// Returns false (for the whole workgroup) if a wait ran past the deadline. Workgroup 0 also
+// rewinds the work ticket of the next pass (`rewind`): its last use, two passes back, is over
+// once every workgroup has arrived.
+__device__ bool grid_barrier(const BatchArgs& a, unsigned long long epoch, unsigned* rewind) {
     __shared__ int s_ok;
     const unsigned long long deadline = wall_clock64() + a.timeout_ticks;
     if (threadIdx.x == 0) s_ok = 1;
@@ -128,6 +127,7 @@ __device__ bool grid_barrier(const BatchArgs& a, unsigned long long epoch) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         if (threadIdx.x == 0 && s_ok) {
+            __hip_atomic_store(rewind, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(&a.ctl->go, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -222,8 +222,8 @@ __device__ __forceinline__ float uniform_f(float x) {
 // per pass.
 template <int K>
 __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) {
-    __shared__ BatchTile s_tiles[kLdsTiles];
-    __shared__ int s_ids[kLdsTiles];
+    __shared__ BatchTile s_tile;
+    __shared__ int s_pos, s_id;
     __shared__ double s_disp[kWavesPerGroup];
     __shared__ float s_mu[kWavesPerGroup], s_mv[kWavesPerGroup];
     constexpr int kOut = batch_strip_out(K);
@@ -234,35 +234,31 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
     const long long base = a.ctl->steps_done;
     const long long pbase = a.ctl->passes_done;
     const int passes = a.steps / K;
-    // this workgroup's tiles: order[first .. first + count), balanced by cost on the host
-    const int2 range = a.wg_range[lwg];
-    const int my_tiles = range.y;
-    auto stage = [&](int k0) {  // descriptors k0 .. k0 + kLdsTiles - 1 of this workgroup
-        const int n = min(kLdsTiles, my_tiles - k0);
-        constexpr int kChunks = sizeof(BatchTile) / 16;
-        for (int e = threadIdx.x; e < n * kChunks; e += kBatchThreads) {
-            const int k = e / kChunks, ch = e - k * kChunks;
-            const int id = a.order[range.x + k0 + k];
-            reinterpret_cast<uint4*>(&s_tiles[k])[ch] = reinterpret_cast<const uint4*>(a.tiles + id)[ch];
-            if (ch == 0) s_ids[k] = id;
-        }
-        __syncthreads();
-    };
-    const bool resident = my_tiles <= kLdsTiles;
-    if (resident) stage(0);
 
     for (int ps = 0; ps < passes; ++ps) {
         const long long step0 = base + (long long)ps * K;  // steps made before this pass
-        const int cur = (int)((pbase + ps) & 1);
+        const long long gpass = pbase + ps;                // passes made before this one
+        const int cur = (int)(gpass & 1);
         if (ps > 0) fold_pass(a, lwg, nwg, ((ps - 1) & 1) * K, step0 - K + 1, K);
         FoldPartial* part = a.part + (size_t)(ps & 1) * K * a.n_tiles;
-        for (int k = 0; k < my_tiles; ++k) {
-            const int kl = k % kLdsTiles;
-            if (!resident && kl == 0) {
-                __syncthreads();
-                stage(k);
+        unsigned* ticket = &a.ctl->next_tile[gpass & 1];
+        // Tiles are handed out costliest first, one per request, so a workgroup that finishes
+        // early takes more of them and every workgroup reaches the barrier at about the same
+        // time. Which workgroup steps a tile changes no bit of any result.
+        for (;;) {
+            if (threadIdx.x == 0)
+                s_pos = (int)__hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int pos = s_pos;
+            if (pos >= a.n_tiles) break;  // the same value in every thread of the workgroup
+            constexpr int kChunks = sizeof(BatchTile) / 16;
+            if (threadIdx.x < kChunks) {
+                const int id = a.order[pos];
+                reinterpret_cast<uint4*>(&s_tile)[threadIdx.x] = reinterpret_cast<const uint4*>(a.tiles + id)[threadIdx.x];
+                if (threadIdx.x == 0) s_id = id;
             }
-            const BatchTile& t = s_tiles[kl];
+            __syncthreads();
+            const BatchTile& t = s_tile;
             const int nx = uniform(t.nx), ny = uniform(t.ny);
             const int group2 = uniform(t.group2);
             const int strip = (group2 >> 1) * kWavesPerGroup + wave;
@@ -296,8 +292,8 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
                         march<true>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, f_disp,
                                     f_mu, f_mv);
                     F[0].disp = f_disp;
-                    F[0].mu_bits = __float_as_uint(f_mu);
-                    F[0].mv_bits = __float_as_uint(f_mv);
+                    F[0].max_u = f_mu;
+                    F[0].max_v = f_mv;
                 } else {
                     if (group2 & 1)
                         marchK<K, false>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, F);
@@ -305,7 +301,7 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
                         marchK<K, true>(e0, u0, v0, hp, e1, u1, v1, nx, ny, c, col_in, out_lane, j0, j1, kc, F);
                 }
             }
-            const int it = s_ids[kl];
+            const int it = s_id;
 #pragma unroll
             for (int s = 0; s < K; ++s) {
                 double f_disp = F[s].disp;
@@ -334,7 +330,7 @@ __global__ __launch_bounds__(kBatchThreads) void sw2d_batch_kernel(BatchArgs a) 
                 __syncthreads();
             }
         }
-        if (!grid_barrier(a, (unsigned long long)(step0 + K))) return;
+        if (!grid_barrier(a, (unsigned long long)(step0 + K), &a.ctl->next_tile[(gpass + 1) & 1])) return;
     }
     fold_pass(a, lwg, nwg, ((passes - 1) & 1) * K, base + (long long)(passes - 1) * K + 1, K);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -358,10 +354,7 @@ struct sw2d_bctx {
     hipStream_t capture;        // private stream used only to record graphs
     BatchInst* d_inst;
     BatchTile* d_tiles;
-    int* d_order;         // tile ids grouped by workgroup
-    int2* d_wg_range;     // [kMaxBatchGrid]
-    std::vector<int> tile_cost;  // per tile: rows marched x strips, the balancing weight
-    int assigned_grid;    // grid the current assignment was made for (-1: none)
+    int* d_order;         // tile ids, costliest first
     FoldPartial* d_part;
     sw2d_red* d_ring;
     BatchControl* d_ctl;
@@ -404,7 +397,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct BatchLayout {
     std::vector<size_t> hp;  // per instance
-    size_t flags, scratch, inst, tiles, order, range, part, ring, ctl, gflags, total;
+    size_t flags, scratch, inst, tiles, order, part, ring, ctl, gflags, total;
     int n_tiles;
     std::vector<int> tiles_of;  // per instance
 };
@@ -456,8 +449,6 @@ bool batch_layout(int n, const sw2d_params* p, const int32_t* band_rows, BatchLa
     off = align_up(off + (size_t)L.n_tiles * sizeof(BatchTile));
     L.order = off;
     off = align_up(off + (size_t)L.n_tiles * sizeof(int));
-    L.range = off;
-    off = align_up(off + (size_t)kMaxBatchGrid * sizeof(int2));
     L.part = off;
     off = align_up(off + 2 * (size_t)kMaxBatchK * L.n_tiles * sizeof(FoldPartial));
     L.ring = off;
@@ -475,7 +466,6 @@ int enqueue_chunks(sw2d_bctx* b, int32_t nsteps, hipStream_t s) {
     a.inst = b->d_inst;
     a.tiles = b->d_tiles;
     a.order = b->d_order;
-    a.wg_range = b->d_wg_range;
     a.part = b->d_part;
     a.ring = b->d_ring;
     a.ctl = b->d_ctl;
@@ -544,48 +534,18 @@ int upload_tiles(sw2d_bctx* b, int K) {
     }
     if (tiles.size() > b->tile_capacity) return SW2D_ENOSPC;
     b->n_tiles = (int)tiles.size();
-    b->tile_cost.swap(cost);
-    b->assigned_grid = -1;
+    // hand-out order: costliest first (rows marched x strips); equal costs keep list order, so
+    // the neighbouring bands of a member go out together
+    std::vector<int> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     SW2D_BHIP(hipMemcpyAsync(b->d_inst, b->inst.data(), b->n * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
     SW2D_BHIP(hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
                              b->stream));
+    if (!order.empty())
+        SW2D_BHIP(hipMemcpyAsync(b->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice,
+                                 b->stream));
     SW2D_BHIP(hipStreamSynchronize(b->stream));
-    return SW2D_OK;
-}
-
-// Balances the tiles over the grid's workgroups by their cost (rows marched x strips):
-// longest first, each to the least loaded workgroup (ties: the lowest index, so runs of
-// equal tiles go to neighbouring workgroups, which share an XCD). Every pass waits for its
-// slowest workgroup, so the largest load sets the pass time.
-int assign_tiles(sw2d_bctx* b) {
-    if (b->assigned_grid == b->grid) return SW2D_OK;
-    const int G = b->grid, n = b->n_tiles;
-    std::vector<int> idx(n);
-    for (int i = 0; i < n; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return b->tile_cost[x] > b->tile_cost[y]; });
-    typedef std::pair<long long, int> Load;  // (load, workgroup)
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-    for (int w = 0; w < G; ++w) heap.push(Load(0, w));
-    std::vector<std::vector<int>> of(G);
-    for (int i : idx) {
-        Load l = heap.top();
-        heap.pop();
-        of[l.second].push_back(i);
-        heap.push(Load(l.first + b->tile_cost[i], l.second));
-    }
-    std::vector<int> order;
-    order.reserve(n);
-    std::vector<int2> range((size_t)G);
-    for (int w = 0; w < G; ++w) {
-        std::sort(of[w].begin(), of[w].end());  // a workgroup walks its tiles in list order
-        range[w] = make_int2((int)order.size(), (int)of[w].size());
-        order.insert(order.end(), of[w].begin(), of[w].end());
-    }
-    SW2D_BHIP(hipStreamSynchronize(b->stream));  // launches in flight read the old assignment
-    if (n > 0) SW2D_BHIP(hipMemcpyAsync(b->d_order, order.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, b->stream));
-    SW2D_BHIP(hipMemcpyAsync(b->d_wg_range, range.data(), (size_t)G * sizeof(int2), hipMemcpyHostToDevice, b->stream));
-    SW2D_BHIP(hipStreamSynchronize(b->stream));
-    b->assigned_grid = G;
     return SW2D_OK;
 }
 
@@ -654,8 +614,6 @@ int sw2d_batch_create(int32_t n, const sw2d_params* p, const float* const* d_H,
     b->d_inst = reinterpret_cast<BatchInst*>(w + L.inst);
     b->d_tiles = reinterpret_cast<BatchTile*>(w + L.tiles);
     b->d_order = reinterpret_cast<int*>(w + L.order);
-    b->d_wg_range = reinterpret_cast<int2*>(w + L.range);
-    b->assigned_grid = -1;
     b->d_flags = reinterpret_cast<unsigned long long*>(w + L.gflags);
     b->d_part = reinterpret_cast<FoldPartial*>(w + L.part);
     b->d_ring = reinterpret_cast<sw2d_red*>(w + L.ring);
@@ -772,8 +730,6 @@ int sw2d_batch_step(sw2d_batch_t b, int32_t nsteps) {
     if (!b || nsteps < 0) return SW2D_ESTATE;
     if (nsteps == 0) return SW2D_OK;
     if (nsteps % b->steps_per_pass != 0) return SW2D_EINVAL;
-    const int rc0 = assign_tiles(b);  // outside any capture: it copies to the device
-    if (rc0) return rc0;
     if (!b->use_graph) {
         int rc = enqueue_chunks(b, nsteps, b->stream);
         if (rc) return rc;
