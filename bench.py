@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--surrogate-fine", type=int, default=4096)
     ap.add_argument("--surrogate-tests", type=int, default=3)
     ap.add_argument("--damping", type=float, default=0.5)
+    ap.add_argument("--noise", type=float, default=0.3,
+                    help="training input noise (normalised units) on eta, u, v")
     ap.add_argument("--surrogate-every", type=int, default=5,
                     help="run the network before every m-th coarse step (trained m coarse steps ahead); "
                          "must divide the judge interval")
@@ -130,7 +132,7 @@ def copy_probe(quiet=False):
 # band heights measured best per workload and steps per pass (sweeps in steps of 4 rows; the
 # throughput is a sawtooth in the band height, from how the last workgroups of a launch fill
 # the GPU)
-TUNED_ROWS = {("basin_8192", 1): 16, ("basin_8192", 2): 16, ("basin_8192", 3): 64, ("basin_8192", 4): 128,
+TUNED_ROWS = {("basin_8192", 1): 8, ("basin_8192", 2): 16, ("basin_8192", 3): 64, ("basin_8192", 4): 128,
               ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 24}
 
 
@@ -320,7 +322,7 @@ def cnn_only_leg(n, log):
 
     ds = S.make_dataset([50000], n=n, pairs_per_run=4, every=20, lead=20)
     net = S.ConvNet(seed=1)
-    trainer = S.Trainer(net, ds, batch=4, noise=0.05)
+    trainer = S.Trainer(net, ds, batch=4, noise=0.3)
     out = _cnn_timings(net, trainer, S.fine_basin(50200, n))
     log(f"cnn kernels: {out}")
     return out
@@ -416,7 +418,7 @@ def surrogate_leg(args, log):
     net = S.ConvNet(seed=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    trainer = S.Trainer(net, ds, batch=4, noise=0.05)
+    trainer = S.Trainer(net, ds, batch=4, noise=args.noise)
     hist = trainer.fit(epochs=args.surrogate_epochs, lr=2e-3)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
@@ -467,7 +469,7 @@ def surrogate_leg(args, log):
         "workload": f"surrogate_{n}: fine {n}^2 (4-cell border, dx=500 m) -> coarse {n // 4}^2, CNN 5-32-32-32-3 "
                     f"3x3 BF16/FP32-acc, {samples} training pairs from {args.surrogate_runs} plain runs, "
                     f"{args.surrogate_epochs} epochs; rollout {n_coarse} coarse steps, judge every {judge}, "
-                    f"threshold {thr} m, damping {args.damping}, network before every "
+                    f"threshold {thr} m, damping {args.damping}, training noise {args.noise}, network before every "
                     f"{args.surrogate_every} coarse step(s)",
         "value_fine_equivalent": round(cells * 4 * n_coarse * len(per) / t_chg / 1e6, 1),
         "unit": "Mcell-steps/s (fine cells x fine steps / wall time incl. fallbacks)",

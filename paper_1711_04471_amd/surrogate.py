@@ -361,7 +361,7 @@ class Trainer:
     uniform noise of amplitude ``noise`` (in normalised units) from the pack kernel, which
     makes the learned correction tolerate the drift of its own rollouts."""
 
-    def __init__(self, net: ConvNet, ds: Dataset, batch=4, noise=0.05):
+    def __init__(self, net: ConvNet, ds: Dataset, batch=4, noise=0.3):
         self.net, self.ds, self.batch, self.noise = net, ds, batch, float(noise)
         self.lib = _lib.load()
         self.dev = net.dev
