@@ -730,9 +730,9 @@ __global__ __launch_bounds__(kWgThreads) void wgrad_kernel(const uint16_t* __res
 }
 
 // dW[i] = sum over chunks of part[chunk][i], in a fixed order: a workgroup takes 32
-// weights, its 8 slices of 32 threads add the chunks k = slice (mod 8) in increasing k, and
-// the 8 slice sums are added in slice order. Entries nw .. nw+31 are the bias.
-constexpr int kRedW = 32, kRedSlices = 8;
+// weights, its 32 slices of 32 threads add the chunks k = slice (mod 32) in increasing k, and
+// the 32 slice sums are added in slice order. Entries nw .. nw+31 are the bias.
+constexpr int kRedW = 32, kRedSlices = 32;
 
 __global__ __launch_bounds__(kRedW* kRedSlices) void wgrad_reduce_kernel(const float* __restrict__ part_w,
                                                                         const float* __restrict__ part_b,
@@ -743,6 +743,7 @@ __global__ __launch_bounds__(kRedW* kRedSlices) void wgrad_reduce_kernel(const f
     const int i = blockIdx.x * kRedW + w;
     float acc = 0.f;
     if (i < nw) {
+#pragma unroll 8
         for (int k = slice; k < chunks; k += kRedSlices) acc += part_w[(size_t)k * nw + i];
     } else if (i < nw + 32) {
         for (int k = slice; k < chunks; k += kRedSlices) acc += part_b[(size_t)k * 32 + (i - nw)];
