@@ -329,11 +329,13 @@ def cnn_only_leg(n, log):
 
 
 def _cnn_timings(net, trainer, case):
-    """Kernel times of the network (HIP events on the stream the library launches on) and
-    their fraction of the dense BF16 peak, counted on the method's own arithmetic (real
-    channel counts, not the padded 16/32 the kernels compute): the one-kernel forward on one
-    coarse image, the weight gradient of a 32 -> 32 layer on the training minibatch, and one
-    whole minibatch of training (forward chain, loss, data and weight gradients, Adam)."""
+    """Kernel times of the network (HIP events on the stream the library launches on) against
+    the roofline that bounds each: the one-kernel forward on one coarse image against the dense
+    BF16 peak, counted on the method's own arithmetic (real channel counts, not the padded 16/32
+    the kernels compute); the weight gradient of a 32 -> 32 layer on the training minibatch
+    against HBM (it reads two 64 B-per-pixel maps for 18,432 FLOP per pixel), with its BF16
+    fraction beside it; and one whole minibatch of training (forward chain, loss, data and
+    weight gradients, Adam) against the BF16 peak."""
     import ctypes
 
     import torch
@@ -364,8 +366,10 @@ def _cnn_timings(net, trainer, case):
         ms = timed(lambda: net.forward_fused(e, u, v, co.H, co.mask, co.ny, co.nx, mp, sp), 50)
         cells = co.nx * co.ny
         tf = cells * CNN_FWD_FLOP_PER_CELL / (ms * 1e-3) / 1e12
+        # the raw state in (eta, u, v, H FP32 and the mask byte) and three FP32 planes out:
+        # 29 B per pixel against 41,472 FLOP, far above the ridge: the matrix cores bound it
         out["forward"] = {"kernel": "cnn_fused_kernel", "image": f"{co.nx}x{co.ny}", "ms": round(ms, 4),
-                          "flop_per_cell": CNN_FWD_FLOP_PER_CELL, "achieved_tflops": round(tf, 1),
+                          "bound": "mfma", "flop_per_cell": CNN_FWD_FLOP_PER_CELL, "achieved_tflops": round(tf, 1),
                           "peak_tflops": BF16_PEAK_TFLOPS, "frac": round(tf / BF16_PEAK_TFLOPS, 4)}
         co.sim.close()
     n, h, w = trainer.batch, trainer.ny, trainer.nx
@@ -377,9 +381,15 @@ def _cnn_timings(net, trainer, case):
                                               trainer.work.numel(), s), 20)
     flop = n * h * w * 2 * 9 * 32 * 32
     tf = flop / (ms * 1e-3) / 1e12
+    # the layer input and its output gradient are read once (BF16 NHWC, 32 channels each):
+    # 128 B per pixel against 18,432 FLOP, 144 FLOP/B, below the BF16 ridge (2.5 PFLOP/s over
+    # 8 TB/s, 312 FLOP/B), so HBM bounds it
+    gbs = n * h * w * 128 / (ms * 1e-3) / 1e9
     out["wgrad_32"] = {"kernel": "wgrad_kernel<32> + wgrad_reduce_kernel", "minibatch": f"{n}x{w}x{h}",
-                       "ms": round(ms, 4), "achieved_tflops": round(tf, 1), "peak_tflops": BF16_PEAK_TFLOPS,
-                       "frac": round(tf / BF16_PEAK_TFLOPS, 4)}
+                       "ms": round(ms, 4), "bound": "hbm", "achieved_gbs": round(gbs, 1), "peak_gbs": HBM_PEAK_GBS,
+                       "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_pixel": 128,
+                       "achieved_tflops": round(tf, 1), "peak_tflops": BF16_PEAK_TFLOPS,
+                       "frac_of_bf16_peak": round(tf / BF16_PEAK_TFLOPS, 4)}
     idx = list(range(n))
 
     def train_step():
