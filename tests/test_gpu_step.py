@@ -84,7 +84,7 @@ def test_basin_2048_1000_steps():
 
 
 # the launch configuration the benchmark times on the 8192^2 basin: steps per pass, band rows
-BENCH_PASS = (4, 104)
+BENCH_PASS = (4, 128)
 
 
 def test_basin_8192_500_steps_full_field():
