@@ -70,10 +70,10 @@ def parse():
     ap.add_argument("--only-surrogate", action="store_true")
     ap.add_argument("--surrogate-runs", type=int, default=20)
     ap.add_argument("--surrogate-pairs", type=int, default=100)
-    ap.add_argument("--surrogate-epochs", type=int, default=18)
+    ap.add_argument("--surrogate-epochs", type=int, default=36)
     ap.add_argument("--surrogate-fine", type=int, default=4096)
     ap.add_argument("--surrogate-tests", type=int, default=3)
-    ap.add_argument("--damping", type=float, default=0.5)
+    ap.add_argument("--damping", type=float, default=0.6)
     ap.add_argument("--noise", type=float, default=0.3,
                     help="training input noise (normalised units) on eta, u, v")
     ap.add_argument("--surrogate-every", type=int, default=5,
@@ -460,6 +460,15 @@ def surrogate_leg(args, log):
                               damping=args.damping, fine=judge_sim, correct_every=args.surrogate_every)
         with fine_sim(case) as judge_sim:
             r_crs = S.rollout(None, case, n_coarse=n_coarse, judge_every=judge, threshold=thr, fine=judge_sim)
+        # accuracy without resets: a fallback restarts a trajectory from the fine state, which
+        # lowers its later judge RMSEs, so the means above compare trajectories with different
+        # reset histories; here neither is ever reset (threshold disabled)
+        with fine_sim(case) as judge_sim:
+            u_cnn = S.rollout(net, case, n_coarse=n_coarse, judge_every=judge, threshold=float("inf"),
+                              damping=args.damping, fine=judge_sim, correct_every=args.surrogate_every).rmse
+        with fine_sim(case) as judge_sim:
+            u_crs = S.rollout(None, case, n_coarse=n_coarse, judge_every=judge, threshold=float("inf"),
+                              fine=judge_sim).rmse
         seg_plain = t_plain / (n_coarse // judge)
         # a segment that fell back is charged at the plain model's cost of that segment
         charged = r_cnn.surrogate_s + r_cnn.fallbacks * seg_plain
@@ -469,7 +478,8 @@ def surrogate_leg(args, log):
                     "fallbacks_coarse_only": r_crs.fallbacks,
                     "t_coarse_only_charged_s": r_crs.surrogate_s + r_crs.fallbacks * seg_plain,
                     "rmse_cnn": [round(x, 6) for x in r_cnn.rmse],
-                    "rmse_coarse_only": [round(x, 6) for x in r_crs.rmse]})
+                    "rmse_coarse_only": [round(x, 6) for x in r_crs.rmse],
+                    "unreset_ratio_cnn_over_coarse_only": [round(c / o, 4) for c, o in zip(u_cnn, u_crs)]})
         log(f"surrogate seed {seed}: {per[-1]}")
     cells = n * n
     t_plain = sum(p["t_plain_s"] for p in per)
@@ -498,6 +508,11 @@ def surrogate_leg(args, log):
         # plain means over every judge: a non-finite judge RMSE makes the mean non-finite
         "mean_rmse_cnn": float(np.mean([x for p in per for x in p["rmse_cnn"]])),
         "mean_rmse_coarse_only": float(np.mean([x for p in per for x in p["rmse_coarse_only"]])),
+        # the same 10 checkpoints per seed with neither trajectory ever reset
+        "unreset_mean_ratio_cnn_over_coarse_only": float(np.mean(
+            [x for p in per for x in p["unreset_ratio_cnn_over_coarse_only"]])),
+        "unreset_max_ratio_cnn_over_coarse_only": float(np.max(
+            [x for p in per for x in p["unreset_ratio_cnn_over_coarse_only"]])),
         "nonfinite_judges_cnn": int(sum(not np.isfinite(x) for p in per for x in p["rmse_cnn"])),
         "nonfinite_judges_coarse_only": int(sum(not np.isfinite(x) for p in per for x in p["rmse_coarse_only"])),
         "train_s": round(train_s, 2), "dataset_s": round(gen_s, 2), "cnn_roofline": cnn, "per_seed": per,

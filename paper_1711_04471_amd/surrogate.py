@@ -437,7 +437,7 @@ class Trainer:
 
 
 def rollout(net: ConvNet | None, case, n_coarse=500, judge_every=50, threshold=1e-3, device="cuda",
-            fine: Sw2d | None = None, damping=0.5, correct_every=1):
+            fine: Sw2d | None = None, damping=0.6, correct_every=1):
     """Advance the surrogate n_coarse coarse steps from the restricted initial state of
     `case`; the fine model judges every judge_every steps and takes over above threshold.
     With net None the coarse model runs alone (the method without the learned part).
