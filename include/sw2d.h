@@ -157,8 +157,9 @@ int64_t sw2d_steps_done(sw2d_t h);
  * the current buffers themselves) and set the step counter. Enqueued on the stream. */
 int sw2d_set_state(sw2d_t h, const float *d_eta, const float *d_u, const float *d_v, int64_t step);
 
-/* Band height (rows per workgroup) of the fused step. Any value in [8, ny] gives the same
- * state bit for bit; it changes speed, and the grouping (not the value) of fold sums. */
+/* Band height (rows per workgroup) of the fused step, 8 (or ny if smaller) by default. Any
+ * value in [8, ny] gives the same state bit for bit; it changes speed, and the grouping (not
+ * the value) of fold sums. */
 int sw2d_set_band_rows(sw2d_t h, int32_t rows);
 int32_t sw2d_band_rows(sw2d_t h);
 
