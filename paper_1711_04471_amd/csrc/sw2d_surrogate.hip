@@ -347,6 +347,15 @@ constexpr int kFuLds = kFuBufA + kFuBufB + 2 * kFuWSlot + kFuBiasBytes;
 constexpr int kFuWPer = (kFuWSlot / 16 + kFuThreads - 1) / kFuThreads;  // 16 B weight chunks per thread
 constexpr int kFuRawPer = (FuRegion<0>::kPix + kFuThreads - 1) / kFuThreads;  // input pixels per thread
 
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of two packed BF16 values: a BF16 with its sign bit set is a negative 16-bit integer,
+// so the signed maximum with 0 zeroes exactly the negative values (and -0). Rounding then
+// clamping equals clamping then rounding, since rounding keeps the sign.
+__device__ __forceinline__ uint32_t relu_bf2(uint32_t w) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2, w), (i16x2){0, 0}));
+}
+
 // The bias pattern of a lane (output channels 8 q + 4 half + e) as an accumulator value.
 __device__ __forceinline__ f32x16 bias_pattern(const float* __restrict__ bias, int half) {
     f32x16 b;
@@ -402,8 +411,8 @@ __device__ __forceinline__ void fused_layer(const unsigned char* __restrict__ in
                 for (int q = 0; q < 4; ++q) {
                     const int n0 = 8 * q + 4 * half;
                     uint2 w;
-                    w.x = f2bf2(fmaxf(acc[4 * q + 0], 0.f), fmaxf(acc[4 * q + 1], 0.f));
-                    w.y = f2bf2(fmaxf(acc[4 * q + 2], 0.f), fmaxf(acc[4 * q + 3], 0.f));
+                    w.x = relu_bf2(f2bf2(acc[4 * q + 0], acc[4 * q + 1]));
+                    w.y = relu_bf2(f2bf2(acc[4 * q + 2], acc[4 * q + 3]));
                     if (!inside) w = make_uint2(0u, 0u);
                     *reinterpret_cast<uint2*>(out_lds + P * Out::kStride + n0 * 2) = w;
                 }
