@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--band-rows", type=int, default=0,
-                    help="band height (default: 16 for single steps, the tuned height for passes)")
+                    help="band height (default: the tuned height for the workload and steps per pass)")
     ap.add_argument("--steps-per-pass", type=int, default=4, choices=[1, 2, 3, 4],
                     help="time steps per pass over the grid (temporal blocking)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
