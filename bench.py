@@ -535,13 +535,13 @@ def variants_leg(case, steps, log):
                         ("advection", ADVECTION), ("all", FRICTION | FILTER_UV | ADVECTION),
                         ("wetdry", WETDRY)):
         with Sw2d.from_case(case, flags=flags, cd=0.0025, hmin=0.0625) as sim:
-            sim.band_rows = 16
+            sim.band_rows = VARIANT_ROWS[name]
             sim.step(10)
             torch.cuda.synchronize()
             ms = sim.step_timed(steps)
         gbs = cells * BYTES_PER_CELL_STEP / (ms * 1e-3) / 1e9
         out[name] = {"ms_per_step": round(ms, 5), "value": round(cells / ms / 1e3, 1),
-                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "band_rows": VARIANT_ROWS[name]}
     # the variants that also take several steps per pass (one column per lane), at their best
     for name, flags in (("friction", FRICTION), ("filter_uv", FILTER_UV), ("wetdry", WETDRY)):
         K, rows = VARIANT_PASS[name]
@@ -592,6 +592,9 @@ def basin2048_leg(steps, log):
     return out
 
 
+# band heights of the single-step variants on the 8192^2 basin (8, 12 and 16 rows measured):
+# 8 rows except with all three of friction, the velocity filter and advection (16)
+VARIANT_ROWS = {"plain": 8, "friction": 8, "filter_uv": 8, "advection": 8, "all": 16, "wetdry": 8}
 # steps per pass and band rows of the variants' K-step passes (best of K = 2..4 x rows 16..64
 # on the 8192^2 basin)
 VARIANT_PASS = {"friction": (2, 32), "filter_uv": (2, 16), "wetdry": (3, 32)}
