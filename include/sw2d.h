@@ -125,8 +125,9 @@ int32_t sw2d_ring_capacity(void);
  * ignored on land), d_mask (uint8 [ny][nx]) are read once; d_state holds 6*nx*ny
  * float32 = two (eta, u, v) buffers, buffer 0 holding the initial state; d_work is
  * the workspace. Checks (SW2D_EINVAL): sizes/constants; border cells must be land;
- * water cells need finite H > 0 and H + eta > 0 (H + eta >= 0 with SW2D_WETDRY); the
- * initial state must be finite;
+ * at least one cell must be water (an all-land grid has nothing to step); water cells
+ * need finite H > 0 and H + eta > 0 (H + eta >= 0 with SW2D_WETDRY); the initial state
+ * must be finite;
  * the Courant number dt sqrt(g H_max) sqrt(1/dx^2 + 1/dy^2) must not exceed 1.
  * Synchronises the stream once. On success *out is a new handle. */
 int sw2d_create(const sw2d_params *p, const float *d_H, const uint8_t *d_mask, float *d_state,

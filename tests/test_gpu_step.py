@@ -149,6 +149,36 @@ def test_deterministic_and_band_height_independent():
         np.testing.assert_allclose(r[3]["max_abs_u"], ored[:, 2], rtol=TOL)
 
 
+@pytest.mark.parametrize("spp", [1, 4])
+def test_degenerate_basins(spp):
+    """The degenerate cases of the method, single steps and 4 steps per pass: a grid that is
+    all land is refused (SW2D_EINVAL: nothing to step), a basin whose only water is one
+    isolated cell keeps that cell's surface bit for bit (no face is active, the filter has no
+    water neighbour, the flux divergence is 0) as the oracle does, and zero steps change
+    nothing."""
+    import dataclasses
+    from paper_1711_04471_amd import _lib
+    c = inputs.small_basin(61, 47, seed=21, steps=12)
+    land = dataclasses.replace(c, name="all_land", mask=np.zeros_like(c.mask), eta=np.zeros_like(c.eta),
+                               u=np.zeros_like(c.u), v=np.zeros_like(c.v))
+    with pytest.raises(_lib.Sw2dError) as ei:
+        gpu_run(land, steps_per_pass=spp, band_rows=8)
+    assert ei.value.code == _lib.SW2D_EINVAL
+    one = np.zeros_like(c.mask)
+    one[20, 30] = 1
+    eta1 = np.zeros_like(c.eta)
+    eta1[20, 30] = 0.25
+    cell = dataclasses.replace(c, name="one_cell", mask=one, eta=eta1, u=np.zeros_like(c.u), v=np.zeros_like(c.v))
+    e, u, v, red = gpu_run(cell, steps_per_pass=spp, band_rows=8)
+    oe, ou, ov, ored = sw2d_ref.run_case(cell, nthreads=NTHREADS)
+    assert np.array_equal(e, oe.astype(np.float32)) and not u.any() and not v.any()
+    assert e[20, 30] == np.float32(0.25) and np.count_nonzero(e) == 1
+    np.testing.assert_allclose(red["vol_disp"], ored[:, 1], rtol=1e-12)
+    e0, u0, v0, red0 = gpu_run(c, nsteps=0)
+    assert red0 is None
+    assert np.array_equal(e0, c.eta) and np.array_equal(u0, c.u) and np.array_equal(v0, c.v)
+
+
 def test_restart_is_bitwise():
     from paper_1711_04471_amd.sw2d import Sw2d
     c = inputs.small_basin(333, 212, seed=43, steps=200)
