@@ -131,3 +131,17 @@ def test_surrogate_entry_points_check_arguments_on_the_host(lib):
     t_std = (ctypes.c_float * 3)(1, 1, 1)
     assert L.sw2d_surrogate_advance(None, 1, dummy, dummy, mean, std, wk, bias, t_std, dummy) == _lib.SW2D_ESTATE
     assert L.sw2d_surrogate_advance_noalloc(None, 1, dummy, dummy, mean, std, wk, bias, t_std) == _lib.SW2D_ESTATE
+
+
+def test_plain_c_client_builds_and_links(lib, tmp_path):
+    """The header compiles as C99 with warnings as errors, and a C program linked against the
+    library and the HIP runtime alone starts (its usage path makes no HIP call)."""
+    import subprocess
+
+    from tests.c_client import build as c_client
+    exe = c_client.build()
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage:" in r.stderr
+    r = subprocess.run([exe, str(tmp_path), "8", "8", "1", "1", "9.81", "0.1", "0.05", "1", "1", "0"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2  # no input files: refused before any device call
