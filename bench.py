@@ -80,6 +80,8 @@ def parse():
                     help="run the network before every m-th coarse step (trained m coarse steps ahead); "
                          "must divide the judge interval")
     ap.add_argument("--no-variants", action="store_true", help="skip the model-variant leg")
+    ap.add_argument("--no-shard", action="store_true",
+                    help="skip the leg that steps one GPU's share of an 8-way row-strip split")
     ap.add_argument("--only-basin2048", action="store_true",
                     help="only the 2048^2 basin (1000 steps at 1, 3 and 4 steps per pass)")
     ap.add_argument("--no-sor", action="store_true", help="skip the SOR pressure-solver leg")
@@ -135,6 +137,11 @@ def copy_probe(quiet=False):
 TUNED_ROWS = {("basin_8192", 1): 8, ("basin_8192", 2): 16, ("basin_8192", 3): 64, ("basin_8192", 4): 128,
               ("basin_2048", 1): 16, ("basin_2048", 2): 16, ("basin_2048", 3): 16, ("basin_2048", 4): 24}
 
+
+# one GPU's share of an 8-way row-strip split of the 8192^2 basin (8192 x 1024 own rows):
+# (steps per pass, band rows) measured best on that shape (K = 3 on 32-row bands, 20.1 us per
+# step; K = 4 at 32 rows 21.2, K = 2 at 48 rows 22.6) and the single step
+SHARD_PASSES = ((3, 32), (1, 8))
 
 # the plain fine model the surrogate is compared with (and judged by): steps per pass, rows
 SURROGATE_PASS = (4, 56)
@@ -557,6 +564,44 @@ def variants_leg(case, steps, log):
             "unit": "Mcell-steps/s", **out}
 
 
+def shard_leg(case, log, parts=8):
+    """The kernel on one GPU's share of a row-strip split of the basin over ``parts`` GPUs, at
+    its real shape: the middle strip's own nx x ny/parts rows plus the halo a pass reads from
+    each neighbour (2K rows at K steps per pass), taken from the basin itself with the outermost
+    row on each side turned to land. The halo exchange is not part of it (one GPU); its size
+    per neighbour and pass is stated beside the measured compute."""
+    import torch
+
+    from paper_1711_04471_amd import inputs
+    from paper_1711_04471_amd.sw2d import Sw2d
+
+    own = case.ny // parts
+    j_lo = (parts // 2 - 1) * own
+    out = {"parts": parts, "own_rows": own, "nx": case.nx, "strip_rows": [j_lo, j_lo + own]}
+    for spp, rows in SHARD_PASSES:
+        halo = 2 * spp
+        strip = inputs.row_strip(case, j_lo, j_lo + own, halo)
+        with Sw2d.from_case(strip) as sim:
+            if spp > 1:
+                sim.set_time_blocking(spp, rows=rows)
+            else:
+                sim.band_rows = rows
+            sim.step(16)
+            torch.cuda.synchronize()
+            ms = sorted(sim.step_timed(96) for _ in range(REPS))[REPS // 2]
+        own_cells = case.nx * own
+        exch = halo * 3 * case.nx * 4  # eta, u, v rows per neighbour and pass (hp once per run)
+        out[f"{spp}_per_pass"] = {
+            "array": f"{strip.nx}x{strip.ny}", "halo_rows": halo, "band_rows": rows,
+            "us_per_step": round(ms * 1e3, 2),
+            "own_Mcell_steps_per_s": round(own_cells / (ms * 1e-3) / 1e6, 1),
+            "halo_exchange_bytes_per_neighbour_per_pass": exch,
+            "halo_exchange_us_at_153GBs": round(exch / 153e9 * 1e6, 2),
+            "compute_us_per_pass": round(ms * spp * 1e3, 2)}
+        log(f"shard {strip.nx}x{strip.ny} K={spp}: {ms * 1e3:.2f} us/step")
+    return out
+
+
 def basin2048_leg(steps, log):
     """The 2048^2 basin (1000 steps with the folds of every step) at one, three and four steps
     per pass. Its working set (eta, u, v twice and H: 117 MB) fits the 256 MB Infinity Cache,
@@ -772,6 +817,8 @@ def main():
                             "max_abs_v": float(red["max_abs_v"][-1])},
     }
     sim.close()
+    if not args.no_shard and args.workload == "basin_8192":
+        out["shard"] = shard_leg(case, log)
     if not args.no_variants:
         out["variants"] = variants_leg(case, min(args.steps, 200), log)
     if not args.no_batched:

@@ -187,6 +187,26 @@ def basin_8192() -> Case:
     return seeded_basin("basin_8192", 8192, 8192, 250.0, seed=3, n_bumps=8, steps=500)
 
 
+def row_strip(case: Case, j_lo: int, j_hi: int, halo: int) -> Case:
+    """Rows [j_lo - halo, j_hi + halo) of ``case``: the rows one GPU of a row-strip split
+    would hold (its own rows j_lo..j_hi-1 and ``halo`` rows of each neighbour), with the
+    outermost row on each side turned to land so that the strip is a closed basin of that
+    shape. Same dx, dt and eps as ``case``."""
+    a, b = j_lo - halo, j_hi + halo
+    if not (0 <= a < b <= case.ny and b - a >= 3):
+        raise ValueError("strip rows outside the grid")
+    mask = case.mask[a:b].copy()
+    mask[0] = 0
+    mask[-1] = 0
+    eta = np.where(mask != 0, case.eta[a:b], 0.0).astype(np.float32)
+    u = np.where(mask != 0, case.u[a:b], 0.0).astype(np.float32)
+    v = np.where(mask != 0, case.v[a:b], 0.0).astype(np.float32)
+    v[-2] = 0.0  # the north face of the last water row now borders land
+    return Case(f"{case.name}_rows{j_lo}-{j_hi}_halo{halo}", case.nx, b - a, case.dx, case.dy, case.g, case.dt,
+                case.eps, case.H[a:b].copy(), mask, eta, u, v, case.steps,
+                meta={**case.meta, "rows": (j_lo, j_hi), "halo": halo})
+
+
 def small_basin(nx: int, ny: int, seed: int, steps: int = 50, n_bumps: int = 3,
                 dx: float = 500.0, eps: float = 0.05) -> Case:
     """A small seeded basin for parity tests (any shape, including ragged tile tails)."""

@@ -1,5 +1,6 @@
 """The seeded input recipe: ranges, land fraction, determinism (host logic only)."""
 import numpy as np
+import pytest
 
 from paper_1711_04471_amd import inputs
 
@@ -36,3 +37,17 @@ def test_ensemble_sizes():
     s = inputs.ensemble_sizes()
     assert len(s) == 256 and all(128 <= a <= 1024 and 128 <= b <= 1024 for a, b in s)
     assert s == inputs.ensemble_sizes()
+
+
+def test_row_strip_is_a_closed_basin_of_the_shard_shape():
+    """One GPU's rows of a row-strip split plus the neighbours' halo rows, taken from the basin,
+    with the outermost row on each side turned to land; everything inside is the basin's own."""
+    c = inputs.small_basin(64, 80, seed=7, steps=5)
+    s = inputs.row_strip(c, 30, 40, 4)
+    assert (s.nx, s.ny) == (64, 18) and s.dt == c.dt and s.dx == c.dx
+    assert not s.mask[0].any() and not s.mask[-1].any() and not s.mask[:, 0].any() and not s.mask[:, -1].any()
+    assert np.array_equal(s.mask[1:-1], c.mask[27:43]) and np.array_equal(s.H, c.H[26:44])
+    assert np.array_equal(s.eta[1:-1], c.eta[27:43]) and not s.eta[0].any() and not s.eta[-1].any()
+    assert not s.v[-2].any()
+    with pytest.raises(ValueError):
+        inputs.row_strip(c, 2, 40, 4)
