@@ -792,6 +792,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 5),
+        # the metric's own % HBM roofline: Mcell-steps/s x 28 B per cell-step / 8 TB/s; above
+        # 100 % when a pass advances several steps (the pass's own fraction is roofline.frac)
+        "hbm_roofline_pct": round(value * 1e6 * BYTES_PER_CELL_STEP / (HBM_PEAK_GBS * 1e9) * 100, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
