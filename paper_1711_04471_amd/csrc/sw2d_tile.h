@@ -417,7 +417,14 @@ __device__ __forceinline__ void row_store(float* base, int r, int nx, unsigned o
 // Rows requested ahead of the one being processed (deeper queues measured no faster).
 constexpr int kRowsAhead = 1;
 
-// Loads rows of one lane's column through a queue of kRowsAhead rows.
+// Loads rows of one lane's column through a queue of kRowsAhead rows. A band's outermost
+// rows feed its output only through some fields: the row two below the band only through its
+// surface, depth and v (its y-face with the row above), the row above the band only through
+// its surface and depth (the y-face below it). Their other fields are read through a
+// zero-size resource (zeros, no memory traffic) when kTrim: skip_u and skip_uv name those
+// rows. (The K-step marches keep every field: there the extra scalar work costs more than the
+// outermost halo rows' traffic.)
+template <bool kTrim = false>
 struct RowLoader {
     const float* __restrict__ eta;
     const float* __restrict__ u;
@@ -425,11 +432,17 @@ struct RowLoader {
     const float* __restrict__ hp;
     int nx, ny, c;
     bool col_in;
+    int skip_u = 0, skip_uv = 0;
     float qe[kRowsAhead], qh[kRowsAhead], qu[kRowsAhead], qv[kRowsAhead];
 
-    __device__ __forceinline__ float load(const float* __restrict__ p, int r) const {
-        return row_load(p, r, nx, ny, col_in ? (unsigned)c * 4u : kNoLane);
+    __device__ __forceinline__ float load(const float* __restrict__ p, int r, int rows) const {
+        return row_load(p, r, nx, rows, col_in ? (unsigned)c * 4u : kNoLane);
     }
+    __device__ __forceinline__ float load(const float* __restrict__ p, int r) const { return load(p, r, ny); }
+    __device__ __forceinline__ float load_u(int r) const {
+        return load(u, r, kTrim && (r == skip_u || r == skip_uv) ? 0 : ny);
+    }
+    __device__ __forceinline__ float load_v(int r) const { return load(v, r, kTrim && r == skip_uv ? 0 : ny); }
     __device__ __forceinline__ void fill(int r_first, int step, int n_rows) {
 #pragma unroll
         for (int d = 0; d < kRowsAhead; ++d) {
@@ -437,8 +450,8 @@ struct RowLoader {
             const bool ok = d < n_rows;
             qe[d] = ok ? load(eta, rr) : 0.f;
             qh[d] = ok ? load(hp, rr) : 0.f;
-            qu[d] = ok ? load(u, rr) : 0.f;
-            qv[d] = ok ? load(v, rr) : 0.f;
+            qu[d] = ok ? load_u(rr) : 0.f;
+            qv[d] = ok ? load_v(rr) : 0.f;
         }
     }
     // Row i (at r) out of the queue; row i + kRowsAhead requested.
@@ -459,8 +472,8 @@ struct RowLoader {
             const int rr = r + kRowsAhead * step;
             qe[kRowsAhead - 1] = load(eta, rr);
             qh[kRowsAhead - 1] = load(hp, rr);
-            qu[kRowsAhead - 1] = load(u, rr);
-            qv[kRowsAhead - 1] = load(v, rr);
+            qu[kRowsAhead - 1] = load_u(rr);
+            qv[kRowsAhead - 1] = load_v(rr);
         }
     }
 };
@@ -507,7 +520,9 @@ __device__ __forceinline__ void march(const float* __restrict__ eta, const float
     constexpr int step = kNorth ? 1 : -1;
     const int r_first = kNorth ? j0 - 2 : j1 + 1;
     const int n_rows = j1 - j0 + 4;
-    RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    RowLoader<true> L{eta, u, v, hp, nx, ny, c, col_in};
+    L.skip_u = j0 - 2;
+    L.skip_uv = j1 + 1;
     const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, step, n_rows);
     Stage<kNorth, kVar> A;
@@ -538,7 +553,7 @@ __device__ __forceinline__ void march_adv(const float* __restrict__ eta, const f
                                           float& f_mu, float& f_mv) {
     const int r_first = j0 - 3;
     const int n_rows = j1 - j0 + 5;
-    RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    RowLoader<> L{eta, u, v, hp, nx, ny, c, col_in};
     const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, 1, n_rows);
     StageAdv<kVar> A;
@@ -574,7 +589,7 @@ __device__ __forceinline__ void marchK(const float* __restrict__ eta, const floa
     constexpr int step = kNorth ? 1 : -1;
     const int r_first = kNorth ? j0 - 2 * K : j1 + 2 * K - 1;
     const int n_rows = j1 - j0 + 4 * K;
-    RowLoader L{eta, u, v, hp, nx, ny, c, col_in};
+    RowLoader<> L{eta, u, v, hp, nx, ny, c, col_in};
     const RowStorer W{eta_o, u_o, v_o, nx, c, out_lane};
     L.fill(r_first, step, n_rows);
     static_assert((kVar & kVarAdvection) == 0, "advection reaches too far for K-step passes");
