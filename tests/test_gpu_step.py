@@ -249,16 +249,21 @@ def test_unfused_three_kernel_split_matches_oracle(shape):
     assert max(rel_l2(e, fe), rel_l2(u, fu), rel_l2(v, fv)) <= 1e-6
 
 
-def test_row_strip_shard_shape():
-    """One GPU's share of a row-strip split at its real shape (the benchmark's shard leg, here
-    an eighth of the 2048^2 basin with the 8 halo rows of 4 steps per pass on each side): 4
-    steps per pass bitwise equal to single steps, both against the oracle."""
-    c = inputs.row_strip(inputs.basin_2048(), 768, 1024, 8)
-    _say(f"case {c.name} {c.nx}x{c.ny}")
-    n = 40
+@pytest.mark.parametrize("basin,spp,rows", [("basin_2048", 4, 128), ("basin_8192", 3, 32)])
+def test_row_strip_shard_shape(basin, spp, rows):
+    """One GPU's share of an 8-way row-strip split at its real shape: an eighth of the 2048^2
+    basin with the 2K halo rows of 4 steps per pass on each side, and the benchmark's shard leg
+    itself (the middle eighth of the 8192^2 basin at 3 steps per pass on 32-row bands). K steps
+    per pass bitwise equal to single steps, both against the oracle."""
+    base = getattr(inputs, basin)()
+    own = base.ny // 8
+    c = inputs.row_strip(base, 3 * own, 4 * own, 2 * spp)
+    del base
+    _say(f"case {c.name} {c.nx}x{c.ny} K={spp} rows={rows}")
+    n = 24
     one = gpu_run(c, nsteps=n, band_rows=8)
-    four = gpu_run(c, nsteps=n, steps_per_pass=4, band_rows=128)
-    assert all(np.array_equal(a, b) for a, b in zip(one[:3], four[:3]))
+    blk = gpu_run(c, nsteps=n, steps_per_pass=spp, band_rows=rows)
+    assert all(np.array_equal(a, b) for a, b in zip(one[:3], blk[:3]))
     oe, ou, ov, ored = sw2d_ref.run_case(c, nsteps=n, nthreads=NTHREADS)
     _check_state(c, *one[:3], oe, ou, ov)
-    np.testing.assert_allclose(four[3]["vol_disp"], ored[:, 1], rtol=TOL, atol=1e-6 * c.dx * c.dy)
+    np.testing.assert_allclose(blk[3]["vol_disp"], ored[:, 1], rtol=TOL, atol=1e-6 * c.dx * c.dy)
