@@ -195,7 +195,14 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(3
     const int j0 = band * geo.rows;
     const int j1 = min(j0 + geo.rows, geo.ny);
 
-    LaneFolds F[K];
+    // per-lane FP64 surface sums of the K steps (see PairFolds)
+    __shared__ double s_disp[K][kGroupThreads];
+    PairFolds F[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        s_disp[s][threadIdx.x] = 0.0;
+        F[s].disp = &s_disp[s][threadIdx.x];
+    }
     if (strip < geo.strips) {
         if (band & 1)  // odd bands march south
             marchK_pair<K, false, kWide>(eta, u, v, hp, eta_o, u_o, v_o, geo.nx, geo.ny, c0, col_in, owned, j0, j1,
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(3
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         if (s > 0) __syncthreads();
-        workgroup_fold(F[s].disp, F[s].mu(), F[s].mv(), part + (size_t)s * stride + blockIdx.x);
+        workgroup_fold(s_disp[s][threadIdx.x], F[s].max_u, F[s].max_v, part + (size_t)s * stride + blockIdx.x);
     }
 }
 

@@ -33,12 +33,12 @@ struct PairCol {
     // esE2, wE2, esW2 and wW2 are the predicted surfaces and water flags east and west of the
     // latter.
     __device__ __forceinline__ void advance(const PairX& X, float hpr, float vr, float esE2, bool wE2, float esW2,
-                                            bool wW2, const StepCoef& k, float& eta_o, float& u_o, float& v_o,
-                                            float& hp_o) {
+                                            bool wW2, bool w3, const StepCoef& k, float& eta_o, float& u_o,
+                                            float& v_o, float& hp_o) {
         u_o = us2;
         v_o = vs2;
         hp_o = hp2;
-        const bool w1 = hp1 > 0.f, w2 = hp2 > 0.f, w3 = hp3 > 0.f;
+        const bool w1 = hp1 > 0.f, w2 = hp2 > 0.f;
         const float h1 = hp1 + e1;  // total depth of row 1, as the x-part computed it
         float vs, fy;
         bool av;
@@ -71,18 +71,20 @@ struct PairCol {
     }
 };
 
-// The east flag of column a is the flag of b and the west flag of b that of a; only the
-// flags across lanes (west of a, east of b) are kept, for rows 1 and 2 behind.
+// The east flag of column a is the flag of b and the west flag of b that of a; the flags
+// across lanes (west of a, east of b) are taken by the caller: those of the input row, and
+// those of the row two behind, which is the next stage's input row.
 template <bool kNorth>
 struct PairStage {
     PairCol<kNorth> a, b;
-    bool aW1 = false, bE1 = false, aW2 = false, bE2 = false;
 
     // Consumes the input row (columns a and b of this lane) and returns the new state of the
-    // row two behind it.
+    // row two behind it. aW, bE: flags west of a and east of b in the input row; aW2, bE2: in
+    // the row two behind; aw3, bw3: the flags of columns a and b three rows behind.
     __device__ __forceinline__ void push(const float (&e)[2], const float (&hp)[2], const float (&ur)[2],
-                                         const float (&vr)[2], const StepCoef& k, float (&eta_o)[2],
-                                         float (&u_o)[2], float (&v_o)[2], float (&hp_o)[2]) {
+                                         const float (&vr)[2], bool aW, bool bE, bool aW2, bool bE2, bool aw3,
+                                         bool bw3, const StepCoef& k, float (&eta_o)[2], float (&u_o)[2],
+                                         float (&v_o)[2], float (&hp_o)[2]) {
         PairX xa, xb;
         xa.e = e[0];
         xb.e = e[1];
@@ -92,9 +94,7 @@ struct PairStage {
         xb.h = hp[1] + e[1];
         // lane exchanges, taken by every lane before any select
         const float eEb = from_east(e[0]), hpEb = from_east(hp[0]);
-        const float hpWa = from_west(hp[1]);
         const float esEb = from_east(a.es2), esWa = from_west(b.es2);
-        const bool bE = hpEb > 0.f, aW = hpWa > 0.f;
         xa.us = x_pred(e[0], e[1], ur[0], xa.w && xb.w, k);
         xb.us = x_pred(e[1], eEb, ur[1], xb.w && bE, k);
         const float fxa = upwind_flux(xa.us, xa.h, xb.h);
@@ -103,14 +103,16 @@ struct PairStage {
         xb.pe = x_update(e[1], fxb, fxa, k);
         const float aes2 = a.es2;
         const bool aw2 = a.hp2 > 0.f, bw2 = b.hp2 > 0.f;
-        a.advance(xa, hp[0], vr[0], b.es2, bw2, esWa, aW2, k, eta_o[0], u_o[0], v_o[0], hp_o[0]);
-        b.advance(xb, hp[1], vr[1], esEb, bE2, aes2, aw2, k, eta_o[1], u_o[1], v_o[1], hp_o[1]);
-        aW2 = aW1;
-        bE2 = bE1;
-        aW1 = aW;
-        bE1 = bE;
+        a.advance(xa, hp[0], vr[0], b.es2, bw2, esWa, aW2, aw3, k, eta_o[0], u_o[0], v_o[0], hp_o[0]);
+        b.advance(xb, hp[1], vr[1], esEb, bE2, aes2, aw2, bw3, k, eta_o[1], u_o[1], v_o[1], hp_o[1]);
     }
 };
+
+// Flags west of column a and east of column b of a row, from the row's depths.
+__device__ __forceinline__ void cross_flags(float hp_a, float hp_b, bool& aW, bool& bE) {
+    aW = from_west(hp_b) > 0.f;
+    bE = from_east(hp_a) > 0.f;
+}
 
 // Rows of a column pair. kWide: nx is even, so a pair never straddles the end of a row and
 // one 8-byte load or store moves it; otherwise each column goes through its own 4-byte
@@ -146,6 +148,25 @@ struct PairIO {
     }
 };
 
+// Folds of one step over this lane's owned pairs: the FP64 surface sum in an LDS slot of
+// this lane (no other lane touches it), updated by an atomic that returns nothing, so it
+// holds no registers across the march; the velocity maxima in registers.
+struct PairFolds {
+    double* disp;
+    float max_u = 0.f, max_v = 0.f;
+    __device__ __forceinline__ void add(const float (&e)[2], const float (&uu)[2], const float (&vv)[2]) {
+        __hip_atomic_fetch_add(disp, (double)e[0] + (double)e[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        max_u = fmaxf(max_u, fmaxf(fabsf(uu[0]), fabsf(uu[1])));
+        max_v = fmaxf(max_v, fmaxf(fabsf(vv[0]), fabsf(vv[1])));
+    }
+};
+
+// Rows requested ahead by the two-column pass at 4 steps per pass. With the folds' FP64 sums in
+// LDS and the flags and depths that neighbouring stages share taken once, two rows ahead fit
+// the register budget of 3 waves per SIMD and measured faster there; at 2 and 3 steps per pass
+// one row ahead measured faster (as in the one-column pipelines).
+constexpr int kPairRowsAhead = 2;
+
 // K steps of a band in one pass with two columns per lane (plain model). c0: column a of
 // this lane; owned: both columns are this lane's output (the b column of a pair straddling
 // an odd row end lies outside the grid, reads land and writes nothing).
@@ -154,9 +175,9 @@ __device__ __forceinline__ void marchK_pair(const float* __restrict__ eta, const
                                             const float* __restrict__ v, const float* __restrict__ hp,
                                             float* __restrict__ eta_o, float* __restrict__ u_o,
                                             float* __restrict__ v_o, int nx, int ny, int c0, bool col_in,
-                                            bool owned, int j0, int j1, const StepCoef& k, LaneFolds* F) {
+                                            bool owned, int j0, int j1, const StepCoef& k, PairFolds* F) {
     constexpr int step = kNorth ? 1 : -1;
-    constexpr int P = kRowsAhead;
+    constexpr int P = K >= 4 ? kPairRowsAhead : 1;
     const int r_first = kNorth ? j0 - 2 * K : j1 + 2 * K - 1;
     const int n_rows = j1 - j0 + 4 * K;
     const PairIO<kWide> io{nx, ny, col_in ? (unsigned)c0 * 4u : kNoLane};
@@ -172,6 +193,7 @@ __device__ __forceinline__ void marchK_pair(const float* __restrict__ eta, const
         io.load(v, rl, qv[d]);
     }
     PairStage<kNorth> S[K];
+    bool lW1 = false, lE1 = false, lW2 = false, lE2 = false;  // last stage: rows 1 and 2 behind
     // One input row; in the priming rows (kSteady false) stage s starts at row 4s (march
     // order) and has valid output from row 4(s+1); in the steady state every stage has.
     auto row = [&](int i, auto steady) {
@@ -202,11 +224,30 @@ __device__ __forceinline__ void marchK_pair(const float* __restrict__ eta, const
             io.load(u, rr, qu[P - 1]);
             io.load(v, rr, qv[P - 1]);
         }
+        // Cross-lane flags of every stage's input row (stage s's row two behind is stage
+        // s + 1's input row, whose depths it already holds), then the last stage's row two
+        // behind, carried from two rows before.
+        bool fW[K + 1], fE[K + 1];
+        cross_flags(h[0], h[1], fW[0], fE[0]);
+#pragma unroll
+        for (int s = 1; s < K; ++s) cross_flags(S[s - 1].a.hp2, S[s - 1].b.hp2, fW[s], fE[s]);
+        fW[K] = lW2;
+        fE[K] = lE2;
+        lW2 = lW1;
+        lE2 = lE1;
+        lW1 = fW[K - 1];
+        lE1 = fE[K - 1];
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             if (!kSteady && s > 0 && i < 4 * s) break;
             float en[2], un[2], vn[2], hn[2];
-            S[s].push(e, h, uu, vv, k, en, un, vn, hn);
+            // Depth three rows behind stage s: its own in the priming rows, then (once every
+            // stage runs) that of the row one behind stage s + 1, the same row.
+            const PairStage<kNorth>& nxt = S[s + 1 < K ? s + 1 : s];
+            const bool shared = kSteady && s + 1 < K;
+            const float h3a = shared ? nxt.a.hp1 : S[s].a.hp3;
+            const float h3b = shared ? nxt.b.hp1 : S[s].b.hp3;
+            S[s].push(e, h, uu, vv, fW[s], fE[s], fW[s + 1], fE[s + 1], h3a > 0.f, h3b > 0.f, k, en, un, vn, hn);
             if (!kSteady && i < 4 * (s + 1)) break;
             const int ro = r - 2 * (s + 1) * step;  // row of stage s's output
             if (kSteady && s == K - 1) {
@@ -214,13 +255,9 @@ __device__ __forceinline__ void marchK_pair(const float* __restrict__ eta, const
                 io.store(eta_o, ro, so, en);
                 io.store(u_o, ro, so, un);
                 io.store(v_o, ro, so, vn);
-                if (owned) {
-                    F[s].add(en[0], un[0], vn[0]);
-                    F[s].add(en[1], un[1], vn[1]);
-                }
+                if (owned) F[s].add(en, un, vn);
             } else if (ro >= j0 && ro < j1 && owned) {
-                F[s].add(en[0], un[0], vn[0]);
-                F[s].add(en[1], un[1], vn[1]);
+                F[s].add(en, un, vn);
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {

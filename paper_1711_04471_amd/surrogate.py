@@ -238,10 +238,11 @@ class Coarse:
         dx, dt = 4 * case.dx, 4 * case.dt
         self.sim = Sw2d(self.nx, self.ny, dx, dx, case.g, dt, case.eps, self.H, self.mask, self.eta, self.u,
                         self.v, device=self.dev)
-        # two steps per pass on 8-row bands: on the 1024^2 coarse grid 7.5 us per step against
-        # 9.7 at one step per pass (and 7.9-8.5 at three or four); the state is that of single steps
+        # three steps per pass on 8-row bands: on the 1024^2 coarse grid, advanced 5 steps per
+        # call as the corrected rollout does, 7.6 us per step against 9.0 at two steps per pass
+        # and 9.1 at four (50 steps per call: 7.2, 7.3, 7.4); the state is that of single steps
         if self.ny >= 8:
-            self.sim.set_time_blocking(2, rows=8)
+            self.sim.set_time_blocking(3, rows=8)
         self.rmse_work = torch.empty(self.lib.sw2d_rmse_workspace_bytes(), dtype=torch.uint8, device=self.dev)
         self.rmse_out = torch.zeros(1, dtype=torch.float64, device=self.dev)
         self.n_wet = int(np.count_nonzero(self.mask.cpu().numpy()))  # host-side count, once
