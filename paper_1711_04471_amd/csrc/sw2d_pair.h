@@ -22,16 +22,17 @@ struct PairX {
 // Pipeline state of one column: rows 1, 2 and 3 behind the one being consumed (march order).
 template <bool kNorth>
 struct PairCol {
-    // The water flags of rows 1 to 3 and the total depth of row 1 are taken again from their
-    // depths where they are used: lane masks kept across the loop would not fit the scalar
-    // registers, and the total depth saves a vector register.
+    // The water flags of rows 1 and 2 and the total depth of row 1 are taken again from their
+    // depths where they are used (lane masks kept across the loop would not fit the scalar
+    // registers, and the total depth saves a vector register); the flag of row 3 comes from
+    // the caller, which takes it from the next stage's row 1 once every stage runs.
     float e1 = 0.f, hp1 = 0.f, v1 = 0.f, pe1 = 0.f, us1 = 0.f, fy1 = 0.f, vs1 = 0.f;
     float es2 = 0.f, fy2 = 0.f, vs2 = 0.f, us2 = 0.f, hp2 = 0.f;
     float es3 = 0.f, hp3 = 0.f;
 
     // y-face, predicted surface of the row one behind, filter output of the row two behind;
     // esE2, wE2, esW2 and wW2 are the predicted surfaces and water flags east and west of the
-    // latter.
+    // latter, w3 the water flag of the row three behind.
     __device__ __forceinline__ void advance(const PairX& X, float hpr, float vr, float esE2, bool wE2, float esW2,
                                             bool wW2, bool w3, const StepCoef& k, float& eta_o, float& u_o,
                                             float& v_o, float& hp_o) {
