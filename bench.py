@@ -139,9 +139,10 @@ TUNED_ROWS = {("basin_8192", 1): 8, ("basin_8192", 2): 16, ("basin_8192", 3): 64
 
 
 # one GPU's share of an 8-way row-strip split of the 8192^2 basin (8192 x 1024 own rows):
-# (steps per pass, band rows) measured best on that shape (K = 3 on 32-row bands, 20.1 us per
-# step; K = 4 at 32 rows 21.2, K = 2 at 48 rows 22.6) and the single step
-SHARD_PASSES = ((3, 32), (1, 8))
+# (steps per pass, band rows) measured best on that shape (K = 3 on 40-row bands, 17.8 us per
+# step; 32 rows 19.1, 24 rows 19.3; K = 4 at 40 rows 17.8, at 32 19.6; K = 2 at 48 rows 22.3)
+# and the single step
+SHARD_PASSES = ((3, 40), (1, 8))
 
 # the plain fine model the surrogate is compared with (and judged by): steps per pass, rows
 SURROGATE_PASS = (4, 56)
